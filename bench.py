@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark: solved LPs/s (and latency) of restarted Halpern PDHG on one MI355X.
+
+A step is one whole solve of a synthetic LP shaped like the paper's large
+MIP-relaxation instances: 150k equality + 50k inequality rows, 1M variables,
+~9.8M nonzeros with power-law row lengths (8..5000) and six decades of row
+scaling, 20% free variables, feasible and bounded by construction.  Inputs
+are resident in HBM (torch tensors) when the timed region starts; each step
+runs lp_create (validation, transpose, scaling, power iteration) and lp_solve
+to a relative KKT error of 1e-4, FP64, r2HPDHG, through the C ABI.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(n, m, nnz, s):
+    """Algorithmic bytes of one plain (non-check) step's two kernels.
+    dual step : K entries (s + 4 B each), row pointers, one read of the
+                gathered 2x+ - x, and the row epilogue (read y, q, y0, write y);
+    primal step: K^T entries, row pointers, one read of the gathered y, and
+                the column epilogue (read x, c, l, u, x0; write xbar, x)."""
+    dual = nnz * (s + 4) + 4 * (m + 1) + s * n + 4 * s * m
+    primal = nnz * (s + 4) + 4 * (n + 1) + s * m + 7 * s * n
+    return primal, dual
+
+
+def cpu_baseline(lp, eta, gpu_iters, gpu_power_iters, method, budget_s=30.0):
+    """Oracle timed on a bounded sample of the same LP (single process):
+    scaling + one epoch of 65 iterations with the GPU's step size, and ten
+    power iterations; extrapolated to a whole solve with the GPU's iteration
+    and power-iteration counts."""
+    import numpy as np
+    import oracle
+    from oracle import core
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    t0 = time.perf_counter()
+    P = core.scaled_problem(lp)
+    t_scale = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.power_iteration(P.K, 0, max_iters=10, min_iters=10, rtol=0.0)
+    t_pw = (time.perf_counter() - t0) / 10.0
+    t0 = time.perf_counter()
+    r = oracle.solve(lp, oracle.Options(method=method, tol=0.0, max_iter=64, eta=eta))
+    t_solve = time.perf_counter() - t0
+    t_iter = max(t_solve - t_scale, 1e-9) / r.iters
+    est = t_scale + gpu_power_iters * t_pw + gpu_iters * t_iter
+    return {"value": 1.0 / est, "unit": "LPs/s", "cores": 1, "kind": "oracle",
+            "sample": (f"same LP: scaling ({t_scale:.1f}s) + 10 power iterations "
+                       f"({t_pw:.3f}s each) + {r.iters} iterations ({t_iter:.3f}s each), "
+                       f"extrapolated to the GPU's {gpu_power_iters} power and {gpu_iters} "
+                       f"solver iterations; est. {est:.0f}s per LP"),
+            "seconds_per_iteration": t_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--method", default="r2hpdhg", choices=["rhpdhg", "r2hpdhg"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--max-iter", type=int, default=2_000_000)
+    ap.add_argument("--workload", default="large", choices=["large", "tiny"])
+    ap.add_argument("--profile-every", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import lpgen
+    import paper_2407_16144_amd as halp
+
+    torch.cuda.set_device(0)
+    lp = lpgen.large_single() if args.workload == "large" else lpgen.tiny()
+    dev = torch.device("cuda", 0)
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+    tens = (T(lp.rowptr, torch.int32), T(lp.col, torch.int32), T(lp.val, torch.float64),
+            T(lp.c, torch.float64), T(lp.rhs, torch.float64), T(lp.lb, torch.float64),
+            T(lp.ub, torch.float64))
+    stream = torch.cuda.current_stream()
+    opt = halp.lp_default_options(
+        method=halp.LP_METHOD_R2HPDHG if args.method == "r2hpdhg" else halp.LP_METHOD_RHPDHG,
+        precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64,
+        profile=args.profile_every)
+
+    def step():
+        h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,
+                           stream=stream.cuda_stream, opt=opt)
+        try:
+            halp.lp_solve(h, args.tol, args.max_iter)
+            r = halp.lp_status(h).as_dict()
+            kt = halp.lp_kernel_times(h)
+        finally:
+            halp.lp_destroy(h)
+        return r, kt
+
+    for i in range(args.warmup):
+        r, _ = step()
+        print(f"warmup {i}: status={halp.STATUS_NAMES[r['status']]} iters={r['iters']} "
+              f"kkt={r['rel_kkt']:.2e} t={r['seconds']:.2f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    lat, results = [], []
+    kp = kd = 0.0
+    kn = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        r, kt = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+        results.append(r)
+        kp += kt[0]
+        kd += kt[1]
+        kn += kt[2]
+        print(f"step {i}: status={halp.STATUS_NAMES[r['status']]} iters={r['iters']} "
+              f"kkt={r['rel_kkt']:.2e} t={lat[-1]:.2f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solved = sum(1 for r in results if r["status"] in (1, 2, 3))
+    value = solved / wall
+    iters = results[-1]["iters"]
+    s = 8 if args.precision == "fp64" else 4
+    bp, bd = algorithmic_bytes(lp.n, lp.m, lp.nnz, s)
+    tp, td = kp / max(kn, 1), kd / max(kn, 1)
+    dom = ("dual_step", bd, td) if td >= tp else ("primal_step", bp, tp)
+    achieved = dom[1] / (dom[2] * 1e-3) / 1e9 if dom[2] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom[0], "bytes_per_launch": int(dom[1]),
+                "avg_ms": {"primal_step": round(tp, 5), "dual_step": round(td, 5)},
+                "timed_steps": kn,
+                "step_achieved_GBs": round((bp + bd) / ((tp + td) * 1e-3) / 1e9, 1) if tp + td > 0 else 0}
+    lat_sorted = sorted(lat)
+    p50 = lat_sorted[len(lat) // 2]
+    p99 = lat_sorted[min(len(lat) - 1, math.ceil(0.99 * len(lat)) - 1)]
+    out = {
+        "metric": "solved LPs/s + p99 latency at 1e-4 rel. KKT; SpMV HBM GB/s vs peak",
+        "value": round(value, 5), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"single LP {lp.m_eq}+{lp.m_ineq} rows x {lp.n} vars, "
+                               f"{lp.nnz} nnz, power-law rows, tol {args.tol:g}",
+                   "method": args.method, "precision": args.precision,
+                   "iterations": iters, "iterations_per_s": round(iters / (wall / args.steps), 1),
+                   "p50_latency_s": round(p50, 3), "p99_latency_s": round(p99, 3),
+                   "rel_kkt": results[-1]["rel_kkt"], "status": halp.STATUS_NAMES[results[-1]["status"]],
+                   "power_iters": results[-1]["power_iters"]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(lp, results[-1]["eta"], iters,
+                                               results[-1]["power_iters"], args.method)
+        except Exception as e:  # pragma: no cover
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

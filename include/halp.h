@@ -1,0 +1,231 @@
+/*
+ * halp.h -- C ABI of an MI355X (gfx950) solver for linear programs based on
+ * restarted Halpern PDHG (rHPDHG) and its reflected variant (r2HPDHG).
+ *
+ * Method: H. Lu and J. Yang, "Restarted Halpern PDHG for Linear Programming",
+ * arXiv 2407.16144 (2024).  The PDHG operator T is Section 2, eq. (pdhg); the
+ * Halpern step eq. (hpdhg); the restarted loop Algorithm 1; the adaptive
+ * restart rule eq. (adaptive-restart) in Section 3; infeasibility
+ * certificates from the infimal displacement vector, Section 5; the reflected
+ * step eq. (hrpdhg) and Algorithm 2 in Section 6; the relative-KKT
+ * termination criterion, preprocessing and primal weight "as cuPDLP" in
+ * Section 7.
+ *
+ * Problem, for every entry point:
+ *
+ *     minimise  c^T x   subject to   A x = b,   G x >= h,   lb <= x <= ub
+ *
+ * given as one CSR matrix K = [A; G] with the m_eq equality rows first and
+ * the m_ineq inequality rows after them, right-hand side rhs = [b; h], and
+ * bounds that may be -INFINITY / +INFINITY.  Duals use the sign in which
+ * y_i >= 0 on inequality rows (Lagrangian c^T x - y^T (K x - rhs)).
+ *
+ * Conventions
+ *  - Every function returns an lp_err code (LP_OK = 0 or a negative error)
+ *    and never aborts; lp_last_error() returns this thread's last message.
+ *  - lp_create / lp_batch_create / lp_server_submit COPY all inputs; the
+ *    caller keeps ownership of its arrays.  With inputs_on_device = 1 every
+ *    array pointer is HIP device memory (e.g. a torch tensor's data_ptr());
+ *    otherwise host memory.
+ *  - Host CSR input may have unsorted or duplicate column indices within a
+ *    row (duplicates are summed).  Device CSR input must have strictly
+ *    increasing column indices within each row.
+ *  - Rejected with LP_ERR_INVALID: n < 1, negative row counts, row_ptr not
+ *    starting at 0 or decreasing, a column index out of range, NaN/Inf in
+ *    val, c or rhs, NaN bounds, lb > ub, lb = +inf or ub = -inf, more than
+ *    2^31 - 1 stored entries.
+ *  - Solutions and certificates are returned in the ORIGINAL (unscaled)
+ *    space, as float64.
+ *  - A handle is not thread-safe.  Different handles may run concurrently
+ *    on different streams.  `stream` is a hipStream_t; NULL makes the
+ *    handle create (and own) a stream of its own.
+ *  - Each handle owns its device memory until it is destroyed.
+ */
+#ifndef HALP_H
+#define HALP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LP_OK = 0,
+  LP_ERR_INVALID = -1, /* bad argument or malformed LP */
+  LP_ERR_OOM = -2,     /* device memory (or reserved capacity) exhausted */
+  LP_ERR_DEVICE = -3,  /* HIP runtime error */
+  LP_ERR_STATE = -4    /* call not valid in the handle's current state */
+} lp_err;
+
+typedef enum {
+  LP_UNSOLVED = 0,
+  LP_OPTIMAL = 1,            /* relative KKT error <= tol at the returned point */
+  LP_PRIMAL_INFEASIBLE = 2,  /* Farkas ray in y-space, see lp_get_certificate */
+  LP_DUAL_INFEASIBLE = 3,    /* unbounded ray in x-space, see lp_get_certificate */
+  LP_ITER_LIMIT = 4,
+  LP_TIME_LIMIT = 5,
+  LP_NUMERICAL = 6           /* NaN or Inf in a reduction */
+} lp_status_code;
+
+typedef enum { LP_METHOD_RHPDHG = 0, LP_METHOD_R2HPDHG = 1 } lp_method;
+typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32 = 1 } lp_precision;
+
+typedef struct {
+  int method;               /* lp_method; default r2HPDHG (Algorithm 2) */
+  int precision;            /* lp_precision; FP32 stores K, K^T and the iterate
+                               streams in float with float accumulation; norms,
+                               KKT, restart and step-size scalars stay float64 */
+  int ruiz_iters;           /* Ruiz infinity-norm passes (default 10) */
+  double pc_alpha;          /* Pock-Chambolle exponent (default 1; <= 0 disables) */
+  int check_every;          /* C: restart / termination checks at k % C == 0 (64) */
+  double restart_beta;      /* adaptive restart factor, 1/e (eq. (adaptive-restart)) */
+  double artificial_restart;/* also restart when k >= this * total (0.36; 0 = off) */
+  double step_safety;       /* eta = step_safety / sigma_hat (0.9) */
+  int power_max_iters;      /* power iteration cap (1000) */
+  int power_min_iters;      /* minimum power iterations (20) */
+  double power_rtol;        /* power iteration stop: relative change (1e-4) */
+  double eps_infeas;        /* relative tolerance of the Farkas tests (1e-8) */
+  int primal_weight;        /* 1: PDLP primal-weight updates; 0: tau = sigma = eta */
+  uint64_t seed;            /* SplitMix64 seed of the power-iteration start */
+  double eta;               /* > 0: fixed step size, power iteration skipped */
+  double omega0;            /* > 0: fixed initial primal weight */
+  int chunk;                /* iterations per launched chunk / graph (64) */
+  int use_graph;            /* 1: replay chunks as a captured hipGraph */
+  int profile;              /* k > 0: time every k-th chunk's two kernels with HIP
+                               events on the solver's stream (see lp_kernel_times) */
+  int verbose;
+} lp_options;
+
+typedef struct {
+  int status;               /* lp_status_code */
+  int ray;                  /* which candidate certified infeasibility: 1 = T(z)-z, 2 = z-z0 */
+  int64_t iters;            /* evaluations of T (one K and one K^T product each) */
+  int64_t restarts;
+  int64_t checks;
+  double pobj, dobj;        /* c^T x and the bound-aware dual objective */
+  double rel_kkt;           /* max of the three relative errors below */
+  double rel_primal, rel_dual, rel_gap;
+  double omega, eta, sigma_hat;
+  int power_iters;
+  double seconds;           /* wall time of the last lp_solve / batch solve */
+} lp_result;
+
+/* Fills *opt with the defaults listed above. */
+void lp_default_options(lp_options* opt);
+
+/* ---------------------------------------------------------------- one LP */
+
+typedef struct lp_solver lp_solver;
+
+/* Copies the LP, builds the explicit transpose K^T, rescales (Ruiz passes and
+ * Pock-Chambolle), estimates ||K~||_2 by power iteration and prepares the
+ * iterates z^{0,0} = (clamp(0, lb, ub), 0).  row_ptr has m_eq + m_ineq + 1
+ * entries, col_idx and val have row_ptr[m] entries, c/lb/ub have n, rhs has
+ * m_eq + m_ineq.  opt may be NULL (defaults).  On success *out owns the
+ * handle. */
+int lp_create(lp_solver** out, int64_t n, int64_t m_eq, int64_t m_ineq, const int32_t* row_ptr,
+              const int32_t* col_idx, const double* val, const double* c, const double* rhs,
+              const double* lb, const double* ub, int inputs_on_device, void* stream,
+              const lp_options* opt);
+
+/* Runs restarted (reflected) Halpern PDHG until the relative KKT error at the
+ * check candidate T(z) is <= rel_kkt_tol (LP_OPTIMAL), an infeasibility
+ * certificate passes its Farkas test, the first check at or after max_iter
+ * evaluations of T (LP_ITER_LIMIT), or time_limit_s seconds (LP_TIME_LIMIT;
+ * < 0 means none).  Checks happen every `check_every` inner iterations, so
+ * the iteration limit is honoured at that granularity.  A handle solves once. */
+int lp_solve(lp_solver* s, double rel_kkt_tol, int64_t max_iter, double time_limit_s);
+
+/* Status and statistics of the last solve. */
+int lp_status(const lp_solver* s, lp_result* out);
+
+/* The candidate of the last check, unscaled: x (n entries), y (m entries).
+ * Either pointer may be NULL.  to_device = 1 writes device memory. */
+int lp_get_solution(const lp_solver* s, double* x, double* y, int to_device);
+
+/* After LP_PRIMAL_INFEASIBLE: a ray y (m entries, y_ineq >= 0) with
+ * rhs^T y > max_{lb<=x<=ub} (K^T y)^T x up to eps_infeas.  After
+ * LP_DUAL_INFEASIBLE: a ray d (n entries) in the recession cone of the box
+ * with c^T d < 0, A d = 0, G d >= 0 up to eps_infeas.  LP_ERR_STATE
+ * otherwise. */
+int lp_get_certificate(const lp_solver* s, double* ray, int to_device);
+
+/* Summed durations (ms) of the primal-step and dual-step kernels over the
+ * steps timed with HIP events (options.profile > 0), and that step count. */
+int lp_kernel_times(const lp_solver* s, double* primal_ms, double* dual_ms, int64_t* steps);
+
+void lp_destroy(lp_solver* s);
+
+/* Message of this thread's last error ("" if none). */
+const char* lp_last_error(void);
+
+/* ---------------------------------------------------------------- batches */
+
+/* One LP of a batch or a serving request; same array conventions as
+ * lp_create. */
+typedef struct {
+  int64_t n, m_eq, m_ineq;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* val;
+  const double* c;
+  const double* rhs;
+  const double* lb;
+  const double* ub;
+} lp_problem;
+
+typedef struct lp_batch lp_batch;
+
+/* Many independent LPs stored as one block-diagonal CSR (per-LP offsets),
+ * advanced together: every step is one launch over all LPs' rows of K^T and
+ * one over all rows of K.  Each LP keeps its own step size, primal weight,
+ * Halpern counter, restart state and status, so an LP's result does not
+ * depend on what else is in the batch. */
+int lp_batch_create(lp_batch** out, int count, const lp_problem* problems, int inputs_on_device,
+                    void* stream, const lp_options* opt);
+/* Solves every LP of the batch (same tolerance and iteration limit). */
+int lp_batch_solve(lp_batch* b, double rel_kkt_tol, int64_t max_iter, double time_limit_s);
+int lp_batch_status(const lp_batch* b, int index, lp_result* out);
+int lp_batch_get_solution(const lp_batch* b, int index, double* x, double* y, int to_device);
+int lp_batch_get_certificate(const lp_batch* b, int index, double* ray, int to_device);
+int lp_batch_kernel_times(const lp_batch* b, double* primal_ms, double* dual_ms, int64_t* steps);
+void lp_batch_destroy(lp_batch* b);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct lp_server lp_server;
+
+/* A continuous-batching solver: submitted LPs wait in a FIFO queue, are
+ * admitted when a slot and enough of the reserved device memory are free,
+ * advance together with every other live LP, and retire as soon as they
+ * finish (results are copied to host memory and their memory is reused).
+ * hbm_budget_bytes bounds the device memory reserved for LP data. */
+int lp_server_create(lp_server** out, int64_t hbm_budget_bytes, int max_slots, void* stream,
+                     const lp_options* opt);
+/* Copies the LP (host arrays) into the queue; *ticket identifies it.
+ * t_arrival is the caller's timestamp (seconds, any origin) used for the
+ * latency figures; LP_ERR_INVALID if the LP alone can never fit. */
+int lp_server_submit(lp_server* s, const lp_problem* p, double rel_kkt_tol, int64_t max_iter,
+                     double t_arrival, int64_t* ticket);
+/* Admits what fits, advances all live LPs by `chunks` chunks, retires the
+ * finished ones.  *n_done receives how many finished during this call. */
+int lp_server_step(lp_server* s, int chunks, int* n_done);
+/* 1 in *done if the ticket has finished (then *out holds its result and
+ * *t_done the server's clock, in the same units as t_arrival). */
+int lp_server_poll(lp_server* s, int64_t ticket, int* done, lp_result* out, double* t_done);
+/* The finished ticket's unscaled solution (host memory). */
+int lp_server_get_solution(lp_server* s, int64_t ticket, double* x, double* y);
+/* Forget a finished ticket. */
+int lp_server_release(lp_server* s, int64_t ticket);
+/* The server's clock: seconds since lp_server_create (use it for t_arrival). */
+int lp_server_clock(const lp_server* s, double* now);
+/* Queue length, live LPs and reserved bytes in use. */
+int lp_server_info(const lp_server* s, int* queued, int* live, int64_t* bytes_in_use);
+void lp_server_destroy(lp_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HALP_H */

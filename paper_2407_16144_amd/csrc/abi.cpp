@@ -1,0 +1,593 @@
+// C ABI over the solver engine (see include/halp.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/halp.h"
+#include "engine.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const halp::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(LP_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(LP_ERR_DEVICE, e.what());
+  }
+}
+
+halp::Options to_opts(const lp_options* o) {
+  halp::Options r;
+  if (!o) return r;
+  r.method = o->method;
+  r.precision = o->precision;
+  r.ruiz_iters = o->ruiz_iters;
+  r.pc_alpha = o->pc_alpha;
+  r.check_every = o->check_every;
+  r.restart_beta = o->restart_beta;
+  r.artificial_restart = o->artificial_restart;
+  r.step_safety = o->step_safety;
+  r.power_max_iters = o->power_max_iters;
+  r.power_min_iters = o->power_min_iters;
+  r.power_rtol = o->power_rtol;
+  r.eps_infeas = o->eps_infeas;
+  r.primal_weight = o->primal_weight;
+  r.seed = o->seed;
+  r.eta = o->eta;
+  r.omega0 = o->omega0;
+  r.chunk = o->chunk;
+  r.use_graph = o->use_graph;
+  r.profile = o->profile;
+  r.verbose = o->verbose;
+  return r;
+}
+
+void check_opts(const halp::Options& o) {
+  if (o.method != 0 && o.method != 1) throw halp::Error(LP_ERR_INVALID, "method must be 0 or 1");
+  if (o.precision != 0 && o.precision != 1) throw halp::Error(LP_ERR_INVALID, "precision must be 0 or 1");
+  if (o.check_every < 1 || o.chunk < 1 || o.chunk > 4096)
+    throw halp::Error(LP_ERR_INVALID, "check_every >= 1 and 1 <= chunk <= 4096 required");
+  if (o.ruiz_iters < 0 || o.power_max_iters < 1 || o.power_min_iters < 1)
+    throw halp::Error(LP_ERR_INVALID, "bad iteration counts");
+  if (!(o.step_safety > 0.0) || !(o.restart_beta > 0.0) || !(o.eps_infeas > 0.0))
+    throw halp::Error(LP_ERR_INVALID, "step_safety, restart_beta and eps_infeas must be positive");
+}
+
+lp_result to_result(const halp::Result& r, double seconds) {
+  lp_result o;
+  std::memset(&o, 0, sizeof(o));
+  o.status = r.status;
+  o.ray = r.ray;
+  o.iters = r.iters;
+  o.restarts = r.restarts;
+  o.checks = r.checks;
+  o.pobj = r.pobj;
+  o.dobj = r.dobj;
+  o.rel_kkt = r.kkt;
+  o.rel_primal = r.rel_p;
+  o.rel_dual = r.rel_d;
+  o.rel_gap = r.rel_gap;
+  o.omega = r.omega;
+  o.eta = r.eta;
+  o.sigma_hat = r.sigma_hat;
+  o.power_iters = r.power_iters;
+  o.seconds = seconds;
+  return o;
+}
+
+halp::Problem to_problem(const lp_problem& p) {
+  halp::Problem q;
+  q.n = p.n;
+  q.m_eq = p.m_eq;
+  q.m_ineq = p.m_ineq;
+  q.rp = p.row_ptr;
+  q.ci = p.col_idx;
+  q.val = p.val;
+  q.c = p.c;
+  q.rhs = p.rhs;
+  q.lb = p.lb;
+  q.ub = p.ub;
+  return q;
+}
+
+int64_t read_nnz(const lp_problem& p, bool on_device) {
+  if (!p.row_ptr) throw halp::Error(LP_ERR_INVALID, "null row_ptr");
+  if (p.m_eq < 0 || p.m_ineq < 0 || p.n < 1)
+    throw halp::Error(LP_ERR_INVALID, "sizes must satisfy n >= 1, m_eq >= 0, m_ineq >= 0");
+  const int64_t m = p.m_eq + p.m_ineq;
+  if (m > INT32_MAX - 2 || p.n > INT32_MAX - 2) throw halp::Error(LP_ERR_INVALID, "dimension too large");
+  int32_t e = 0;
+  if (on_device) {
+    if (hipMemcpy(&e, p.row_ptr + m, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      throw halp::Error(LP_ERR_DEVICE, "cannot read row_ptr[m] from device");
+  } else {
+    e = p.row_ptr[m];
+  }
+  if (e < 0) throw halp::Error(LP_ERR_INVALID, "row_ptr[m] must be >= 0");
+  return e;
+}
+
+struct StreamHolder {
+  hipStream_t s = nullptr;
+  bool own = false;
+  void init(void* user) {
+    if (user) {
+      s = (hipStream_t)user;
+    } else {
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        throw halp::Error(LP_ERR_DEVICE, "hipStreamCreate failed");
+      own = true;
+    }
+  }
+  ~StreamHolder() {
+    if (own && s) (void)hipStreamDestroy(s);
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct lp_solver {
+  StreamHolder stream;
+  std::unique_ptr<halp::EngineBase> eng;
+  int id = -1;
+  bool solved = false;
+  double seconds = 0.0;
+};
+
+struct lp_batch {
+  StreamHolder stream;
+  std::unique_ptr<halp::EngineBase> eng;
+  std::vector<int> ids;
+  double seconds = 0.0;
+};
+
+extern "C" {
+
+void lp_default_options(lp_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  halp::Options d;
+  o->method = d.method;
+  o->precision = d.precision;
+  o->ruiz_iters = d.ruiz_iters;
+  o->pc_alpha = d.pc_alpha;
+  o->check_every = d.check_every;
+  o->restart_beta = d.restart_beta;
+  o->artificial_restart = d.artificial_restart;
+  o->step_safety = d.step_safety;
+  o->power_max_iters = d.power_max_iters;
+  o->power_min_iters = d.power_min_iters;
+  o->power_rtol = d.power_rtol;
+  o->eps_infeas = d.eps_infeas;
+  o->primal_weight = d.primal_weight;
+  o->seed = d.seed;
+  o->eta = d.eta;
+  o->omega0 = d.omega0;
+  o->chunk = d.chunk;
+  o->use_graph = d.use_graph;
+  o->profile = d.profile;
+  o->verbose = d.verbose;
+}
+
+const char* lp_last_error(void) { return g_err.c_str(); }
+
+int lp_create(lp_solver** out, int64_t n, int64_t m_eq, int64_t m_ineq, const int32_t* row_ptr,
+              const int32_t* col_idx, const double* val, const double* c, const double* rhs, const double* lb,
+              const double* ub, int inputs_on_device, void* stream, const lp_options* opt) {
+  return guarded([&]() -> int {
+    if (!out) return fail(LP_ERR_INVALID, "null output handle");
+    *out = nullptr;
+    lp_problem p{n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub};
+    const halp::Options o = to_opts(opt);
+    check_opts(o);
+    const int64_t nnz = read_nnz(p, inputs_on_device != 0);
+    if (!inputs_on_device) halp::validate_host_problem(to_problem(p));
+    std::unique_ptr<lp_solver> s(new lp_solver());
+    s->stream.init(stream);
+    s->eng = halp::make_engine(o, s->stream.s, m_eq + m_ineq + 1, n + 1, nnz, 1);
+    s->id = s->eng->add({to_problem(p)}, inputs_on_device != 0)[0];
+    *out = s.release();
+    return LP_OK;
+  });
+}
+
+int lp_solve(lp_solver* s, double tol, int64_t max_iter, double time_limit_s) {
+  return guarded([&]() -> int {
+    if (!s) return fail(LP_ERR_INVALID, "null handle");
+    if (s->solved) return fail(LP_ERR_STATE, "this handle has already solved its LP");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
+    const double t0 = now_s();
+    s->eng->set_params({s->id}, tol, max_iter);
+    s->eng->run(time_limit_s);
+    s->seconds = now_s() - t0;
+    s->solved = true;
+    return LP_OK;
+  });
+}
+
+int lp_status(const lp_solver* s, lp_result* out) {
+  return guarded([&]() -> int {
+    if (!s || !out) return fail(LP_ERR_INVALID, "null argument");
+    *out = to_result(s->eng->result(s->id), s->seconds);
+    return LP_OK;
+  });
+}
+
+int lp_get_solution(const lp_solver* s, double* x, double* y, int to_device) {
+  return guarded([&]() -> int {
+    if (!s) return fail(LP_ERR_INVALID, "null handle");
+    if (!s->solved) return fail(LP_ERR_STATE, "solve first");
+    s->eng->solution(s->id, x, y, to_device != 0);
+    return LP_OK;
+  });
+}
+
+int lp_get_certificate(const lp_solver* s, double* ray, int to_device) {
+  return guarded([&]() -> int {
+    if (!s || !ray) return fail(LP_ERR_INVALID, "null argument");
+    if (!s->solved) return fail(LP_ERR_STATE, "solve first");
+    s->eng->certificate(s->id, ray, to_device != 0);
+    return LP_OK;
+  });
+}
+
+int lp_kernel_times(const lp_solver* s, double* primal_ms, double* dual_ms, int64_t* steps) {
+  return guarded([&]() -> int {
+    if (!s || !primal_ms || !dual_ms || !steps) return fail(LP_ERR_INVALID, "null argument");
+    const halp::KernelTimes t = s->eng->kernel_times();
+    *primal_ms = t.primal_ms;
+    *dual_ms = t.dual_ms;
+    *steps = t.launches;
+    return LP_OK;
+  });
+}
+
+void lp_destroy(lp_solver* s) {
+  try {
+    delete s;
+  } catch (...) {
+  }
+}
+
+// ------------------------------------------------------------------ batch
+
+int lp_batch_create(lp_batch** out, int count, const lp_problem* problems, int inputs_on_device, void* stream,
+                    const lp_options* opt) {
+  return guarded([&]() -> int {
+    if (!out || (count > 0 && !problems) || count < 1) return fail(LP_ERR_INVALID, "need count >= 1 problems");
+    *out = nullptr;
+    const halp::Options o = to_opts(opt);
+    check_opts(o);
+    int64_t ms = 0, ns = 0, zs = 0;
+    std::vector<halp::Problem> ps;
+    for (int i = 0; i < count; ++i) {
+      const int64_t nnz = read_nnz(problems[i], inputs_on_device != 0);
+      if (!inputs_on_device) halp::validate_host_problem(to_problem(problems[i]));
+      ms += problems[i].m_eq + problems[i].m_ineq + 1;
+      ns += problems[i].n + 1;
+      zs += nnz;
+      ps.push_back(to_problem(problems[i]));
+    }
+    if (zs > INT32_MAX) return fail(LP_ERR_INVALID, "batch holds more than 2^31 - 1 entries");
+    std::unique_ptr<lp_batch> b(new lp_batch());
+    b->stream.init(stream);
+    b->eng = halp::make_engine(o, b->stream.s, ms, ns, zs, count);
+    b->ids = b->eng->add(ps, inputs_on_device != 0);
+    *out = b.release();
+    return LP_OK;
+  });
+}
+
+int lp_batch_solve(lp_batch* b, double tol, int64_t max_iter, double time_limit_s) {
+  return guarded([&]() -> int {
+    if (!b) return fail(LP_ERR_INVALID, "null handle");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
+    const double t0 = now_s();
+    b->eng->set_params(b->ids, tol, max_iter);
+    b->eng->run(time_limit_s);
+    b->seconds = now_s() - t0;
+    return LP_OK;
+  });
+}
+
+int lp_batch_status(const lp_batch* b, int index, lp_result* out) {
+  return guarded([&]() -> int {
+    if (!b || !out || index < 0 || index >= (int)b->ids.size()) return fail(LP_ERR_INVALID, "bad argument");
+    *out = to_result(b->eng->result(b->ids[index]), b->seconds);
+    return LP_OK;
+  });
+}
+
+int lp_batch_get_solution(const lp_batch* b, int index, double* x, double* y, int to_device) {
+  return guarded([&]() -> int {
+    if (!b || index < 0 || index >= (int)b->ids.size()) return fail(LP_ERR_INVALID, "bad argument");
+    b->eng->solution(b->ids[index], x, y, to_device != 0);
+    return LP_OK;
+  });
+}
+
+int lp_batch_get_certificate(const lp_batch* b, int index, double* ray, int to_device) {
+  return guarded([&]() -> int {
+    if (!b || !ray || index < 0 || index >= (int)b->ids.size()) return fail(LP_ERR_INVALID, "bad argument");
+    b->eng->certificate(b->ids[index], ray, to_device != 0);
+    return LP_OK;
+  });
+}
+
+int lp_batch_kernel_times(const lp_batch* b, double* primal_ms, double* dual_ms, int64_t* steps) {
+  return guarded([&]() -> int {
+    if (!b || !primal_ms || !dual_ms || !steps) return fail(LP_ERR_INVALID, "null argument");
+    const halp::KernelTimes t = b->eng->kernel_times();
+    *primal_ms = t.primal_ms;
+    *dual_ms = t.dual_ms;
+    *steps = t.launches;
+    return LP_OK;
+  });
+}
+
+void lp_batch_destroy(lp_batch* b) {
+  try {
+    delete b;
+  } catch (...) {
+  }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ serving
+
+namespace {
+
+struct Request {
+  int64_t ticket = 0;
+  int64_t n = 0, m_eq = 0, m_ineq = 0, nnz = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> val, c, rhs, lb, ub;
+  double tol = 1e-4;
+  int64_t max_iter = 1;
+  double t_arrival = 0.0;
+  int slot = -1;
+  bool done = false;
+  lp_result res{};
+  double t_done = 0.0;
+  std::vector<double> x, y;
+};
+
+}  // namespace
+
+struct lp_server {
+  StreamHolder stream;
+  std::unique_ptr<halp::EngineBase> eng;
+  int64_t budget = 0;
+  int max_slots = 0;
+  int64_t next_ticket = 1;
+  std::deque<int64_t> queue;
+  std::map<int64_t, Request> reqs;
+  std::map<int, int64_t> slot_ticket;
+  double t0 = 0.0;
+  double clock() const { return now_s() - t0; }
+};
+
+extern "C" {
+
+int lp_server_create(lp_server** out, int64_t budget, int max_slots, void* stream, const lp_options* opt) {
+  return guarded([&]() -> int {
+    if (!out || budget <= 0 || max_slots < 1) return fail(LP_ERR_INVALID, "need budget > 0 and max_slots >= 1");
+    *out = nullptr;
+    const halp::Options o = to_opts(opt);
+    check_opts(o);
+    std::unique_ptr<lp_server> s(new lp_server());
+    s->stream.init(stream);
+    // split the budget over the three spaces for a reference mix of
+    // n = 4 m and nnz = 36 m (sizes of the batched workload)
+    const int64_t sz = o.precision == 1 ? 4 : 8;
+    const int64_t per_row = 4 + 24 + 9 * sz, per_col = 4 + 40 + 10 * sz;
+    const int64_t per_nz = 24 + (o.precision == 1 ? 8 : 0);
+    const int64_t unit = per_row + 4 * per_col + 36 * per_nz;
+    const int64_t u = budget / unit;
+    if (u < 16) return fail(LP_ERR_INVALID, "budget too small");
+    const int64_t cap_nz = std::min<int64_t>(36 * u, INT32_MAX - 1);
+    s->budget = budget;
+    s->max_slots = max_slots;
+    s->eng = halp::make_engine(o, s->stream.s, u + max_slots, 4 * u + max_slots, cap_nz, max_slots);
+    s->t0 = now_s();
+    *out = s.release();
+    return LP_OK;
+  });
+}
+
+int lp_server_submit(lp_server* s, const lp_problem* p, double tol, int64_t max_iter, double t_arrival,
+                     int64_t* ticket) {
+  return guarded([&]() -> int {
+    if (!s || !p || !ticket) return fail(LP_ERR_INVALID, "null argument");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
+    const int64_t nnz = read_nnz(*p, false);
+    const int64_t m = p->m_eq + p->m_ineq;
+    Request r;
+    r.ticket = s->next_ticket++;
+    r.n = p->n;
+    r.m_eq = p->m_eq;
+    r.m_ineq = p->m_ineq;
+    r.nnz = nnz;
+    r.rp.assign(p->row_ptr, p->row_ptr + m + 1);
+    if (nnz) {
+      if (!p->col_idx || !p->val) return fail(LP_ERR_INVALID, "null column or value array");
+      r.ci.assign(p->col_idx, p->col_idx + nnz);
+      r.val.assign(p->val, p->val + nnz);
+    }
+    if (!p->c || !p->lb || !p->ub || (m && !p->rhs)) return fail(LP_ERR_INVALID, "null vector");
+    r.c.assign(p->c, p->c + p->n);
+    r.lb.assign(p->lb, p->lb + p->n);
+    r.ub.assign(p->ub, p->ub + p->n);
+    if (m) r.rhs.assign(p->rhs, p->rhs + m);
+    halp::validate_host_problem(to_problem(*p));
+    r.tol = tol;
+    r.max_iter = max_iter;
+    r.t_arrival = t_arrival;
+    if (s->eng->live() == 0 && !s->eng->fits(r.n, m, nnz))
+      return fail(LP_ERR_INVALID, "LP is larger than the server's reserved memory");
+    *ticket = r.ticket;
+    s->queue.push_back(r.ticket);
+    s->reqs.emplace(r.ticket, std::move(r));
+    return LP_OK;
+  });
+}
+
+int lp_server_step(lp_server* s, int chunks, int* n_done) {
+  return guarded([&]() -> int {
+    if (!s || chunks < 0) return fail(LP_ERR_INVALID, "bad argument");
+    // admission: every queued LP that fits, in arrival order
+    std::vector<halp::Problem> ps;
+    std::vector<int64_t> tk;
+    std::deque<int64_t> rest;
+    int free_slots = s->max_slots - s->eng->live();
+    for (int64_t t : s->queue) {
+      Request& r = s->reqs.at(t);
+      const int64_t m = r.m_eq + r.m_ineq;
+      // conservative: the engine checks each space for one LP at a time, so
+      // admit one by one
+      if ((int)ps.size() < free_slots && s->eng->fits(r.n, m, r.nnz)) {
+        halp::Problem q;
+        q.n = r.n;
+        q.m_eq = r.m_eq;
+        q.m_ineq = r.m_ineq;
+        q.rp = r.rp.data();
+        q.ci = r.ci.data();
+        q.val = r.val.data();
+        q.c = r.c.data();
+        q.rhs = r.rhs.data();
+        q.lb = r.lb.data();
+        q.ub = r.ub.data();
+        std::vector<int> id = s->eng->add({q}, false);
+        s->eng->set_params(id, r.tol, r.max_iter);
+        r.slot = id[0];
+        s->slot_ticket[id[0]] = t;
+        ps.push_back(q);
+        tk.push_back(t);
+      } else {
+        rest.push_back(t);
+      }
+    }
+    s->queue.swap(rest);
+    int nd = 0;
+    if (s->eng->live() > 0 && chunks > 0) {
+      std::vector<int> done = s->eng->advance(chunks);
+      const double tnow = s->clock();
+      for (int slot : done) {
+        const int64_t t = s->slot_ticket.at(slot);
+        Request& r = s->reqs.at(t);
+        r.res = to_result(s->eng->result(slot), 0.0);
+        r.x.resize(r.n);
+        r.y.resize(r.m_eq + r.m_ineq);
+        s->eng->solution(slot, r.x.data(), r.y.empty() ? nullptr : r.y.data(), false);
+        r.t_done = tnow;
+        r.done = true;
+        r.slot = -1;
+        s->slot_ticket.erase(slot);
+        s->eng->remove({slot});
+        // drop the input copy
+        std::vector<int32_t>().swap(r.rp);
+        std::vector<int32_t>().swap(r.ci);
+        std::vector<double>().swap(r.val);
+        ++nd;
+      }
+    }
+    if (n_done) *n_done = nd;
+    return LP_OK;
+  });
+}
+
+int lp_server_poll(lp_server* s, int64_t ticket, int* done, lp_result* out, double* t_done) {
+  return guarded([&]() -> int {
+    if (!s || !done) return fail(LP_ERR_INVALID, "null argument");
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(LP_ERR_INVALID, "unknown ticket");
+    *done = it->second.done ? 1 : 0;
+    if (it->second.done) {
+      if (out) *out = it->second.res;
+      if (t_done) *t_done = it->second.t_done;
+    }
+    return LP_OK;
+  });
+}
+
+int lp_server_get_solution(lp_server* s, int64_t ticket, double* x, double* y) {
+  return guarded([&]() -> int {
+    if (!s) return fail(LP_ERR_INVALID, "null handle");
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(LP_ERR_INVALID, "unknown ticket");
+    if (!it->second.done) return fail(LP_ERR_STATE, "ticket not finished");
+    if (x) std::memcpy(x, it->second.x.data(), sizeof(double) * it->second.x.size());
+    if (y && !it->second.y.empty()) std::memcpy(y, it->second.y.data(), sizeof(double) * it->second.y.size());
+    return LP_OK;
+  });
+}
+
+int lp_server_release(lp_server* s, int64_t ticket) {
+  return guarded([&]() -> int {
+    if (!s) return fail(LP_ERR_INVALID, "null handle");
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(LP_ERR_INVALID, "unknown ticket");
+    if (!it->second.done) return fail(LP_ERR_STATE, "ticket not finished");
+    s->reqs.erase(it);
+    return LP_OK;
+  });
+}
+
+int lp_server_clock(const lp_server* s, double* now) {
+  return guarded([&]() -> int {
+    if (!s || !now) return fail(LP_ERR_INVALID, "null argument");
+    *now = s->clock();
+    return LP_OK;
+  });
+}
+
+int lp_server_info(const lp_server* s, int* queued, int* live, int64_t* bytes) {
+  return guarded([&]() -> int {
+    if (!s) return fail(LP_ERR_INVALID, "null handle");
+    if (queued) *queued = (int)s->queue.size();
+    if (live) *live = s->eng->live();
+    if (bytes) {
+      int64_t b = 0;
+      for (auto& kv : s->slot_ticket) {
+        const Request& r = s->reqs.at(kv.second);
+        b += s->eng->footprint(r.n, r.m_eq + r.m_ineq, r.nnz);
+      }
+      *bytes = b;
+    }
+    return LP_OK;
+  });
+}
+
+void lp_server_destroy(lp_server* s) {
+  try {
+    delete s;
+  } catch (...) {
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Host-side solver engine: device storage for a set of LPs ("instances"),
+// preprocessing, power iteration, and the chunked iteration loop.  A single
+// LP is an engine holding one instance; the batched and serving front ends
+// hold many.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "halp_types.h"
+
+namespace halp {
+
+struct Problem {  // one input LP; pointers are host or device memory
+  int64_t n = 0, m_eq = 0, m_ineq = 0;
+  const int32_t* rp = nullptr;
+  const int32_t* ci = nullptr;
+  const double* val = nullptr;
+  const double* c = nullptr;
+  const double* rhs = nullptr;
+  const double* lb = nullptr;
+  const double* ub = nullptr;
+};
+
+struct Options {
+  int method = 1;  // 0 rHPDHG, 1 r2HPDHG
+  int precision = 0;  // 0 fp64, 1 fp32
+  int ruiz_iters = 10;
+  double pc_alpha = 1.0;
+  int check_every = 64;
+  double restart_beta = 0.36787944117144233;
+  double artificial_restart = 0.36;
+  double step_safety = 0.9;
+  int power_max_iters = 1000;
+  int power_min_iters = 20;
+  double power_rtol = 1e-4;
+  double eps_infeas = 1e-8;
+  int primal_weight = 1;
+  uint64_t seed = 0;
+  double eta = 0.0;
+  double omega0 = 0.0;
+  int chunk = 64;
+  int use_graph = 1;
+  int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
+  int verbose = 0;
+};
+
+struct KernelTimes {
+  double primal_ms = 0.0, dual_ms = 0.0;  // summed over timed launches
+  int64_t launches = 0;                   // timed steps (one primal + one dual launch each)
+};
+
+struct Result {
+  int status = 0;
+  int64_t iters = 0, restarts = 0, checks = 0;
+  double kkt = 0, rel_p = 0, rel_d = 0, rel_gap = 0, pobj = 0, dobj = 0, resid = 0;
+  double omega = 0, eta = 0, sigma_hat = 0;
+  int power_iters = 0, ray = 0;
+  double seconds = 0;
+};
+
+class Error : public std::runtime_error {
+ public:
+  Error(int code, const std::string& msg) : std::runtime_error(msg), code(code) {}
+  int code;
+};
+
+class EngineBase {
+ public:
+  virtual ~EngineBase() = default;
+  // add LPs (validated, preprocessed, iterates initialised); returns slot ids
+  virtual std::vector<int> add(const std::vector<Problem>& probs, bool on_device) = 0;
+  virtual void set_params(const std::vector<int>& ids, double tol, int64_t max_iter) = 0;
+  // run until every listed slot has terminated (or the time limit)
+  virtual void run(double time_limit_s) = 0;
+  // advance all live slots by `chunks` chunks; returns slots that finished since last call
+  virtual std::vector<int> advance(int chunks) = 0;
+  virtual void remove(const std::vector<int>& ids) = 0;
+  virtual Result result(int id) = 0;
+  virtual void solution(int id, double* x, double* y, bool to_device) = 0;
+  virtual void certificate(int id, double* ray, bool to_device) = 0;
+  virtual int64_t n_of(int id) const = 0;
+  virtual int64_t m_of(int id) const = 0;
+  virtual int live() const = 0;
+  virtual hipStream_t stream() const = 0;
+  // bytes of device storage an LP of this size needs (admission control)
+  virtual int64_t footprint(int64_t n, int64_t m, int64_t nnz) const = 0;
+  virtual bool fits(int64_t n, int64_t m, int64_t nnz) const = 0;
+  virtual KernelTimes kernel_times() const = 0;
+};
+
+// Host-side validation of a host-memory LP (throws Error(-1, ...)); needs no GPU.
+void validate_host_problem(const Problem& p);
+
+// capacity: sizes of the three spaces and the slot count (0 = grow to fit)
+std::unique_ptr<EngineBase> make_engine(const Options& opt, hipStream_t stream, int64_t cap_m,
+                                        int64_t cap_n, int64_t cap_nnz, int max_slots);
+
+}  // namespace halp

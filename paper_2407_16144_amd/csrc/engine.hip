@@ -1,0 +1,1113 @@
+// Host-side engine of the HIP solver.  This translation unit also holds the
+// kernels (included below), so every launch resolves inside one code object.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "kernels.hip"
+
+namespace halp {
+
+#define HIPCHECK(expr)                                                                       \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw Error(-3, std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// first-fit allocator over one space
+class RangeAlloc {
+ public:
+  explicit RangeAlloc(int64_t cap = 0) : cap_(cap) {
+    if (cap > 0) free_[0] = cap;
+  }
+  int64_t alloc(int64_t len) {
+    if (len <= 0) return 0;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= len) {
+        const int64_t at = it->first, rest = it->second - len;
+        free_.erase(it);
+        if (rest > 0) free_[at + len] = rest;
+        return at;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t at, int64_t len) {
+    if (len <= 0) return;
+    auto it = free_.emplace(at, len).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  bool can(int64_t len) const {
+    if (len <= 0) return true;
+    for (auto& kv : free_)
+      if (kv.second >= len) return true;
+    return false;
+  }
+
+ private:
+  int64_t cap_;
+  std::map<int64_t, int64_t> free_;
+};
+
+template <class P>
+static void dalloc(P** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, sizeof(P) * (size_t)count);
+  if (e != hipSuccess) throw Error(-2, std::string("device allocation failed: ") + hipGetErrorString(e));
+}
+
+template <class P>
+static void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// Workgroup schedule of one LP's rows: consecutive rows are packed into
+// "stream" blocks of at most NB entries and kMaxRows rows; a row with more
+// than NB entries gets a "long" block.  Every LP gets at least one block so
+// that its controller always runs.
+static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int inst, int NB,
+                         std::vector<Blk>& out) {
+  const size_t first = out.size();
+  int64_t start = 0, acc = 0;
+  auto flush = [&](int64_t a, int64_t b) {
+    if (b > a) out.push_back(Blk{(int32_t)(base + a), (int32_t)(base + b), inst, BK_STREAM});
+  };
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t len = (int64_t)rp[r + 1] - rp[r];
+    if (len > NB) {
+      flush(start, r);
+      out.push_back(Blk{(int32_t)(base + r), (int32_t)(base + r + 1), inst, BK_LONG});
+      start = r + 1;
+      acc = 0;
+      continue;
+    }
+    if (acc + len > NB || (r - start) >= kMaxRows) {
+      flush(start, r);
+      start = r;
+      acc = 0;
+    }
+    acc += len;
+  }
+  flush(start, nrows);
+  if (out.size() == first) out.push_back(Blk{(int32_t)base, (int32_t)base, inst, BK_STREAM});
+}
+
+struct Slot {
+  bool used = false;
+  int64_t n = 0, m = 0, m_eq = 0, nnz = 0;
+  int64_t row0 = 0, col0 = 0, nz0 = 0;
+  std::vector<Blk> bP, bD;  // block lists (inst field = slot id)
+  bool watched = false;
+  bool reported = false;
+};
+
+template <class T>
+class Engine final : public EngineBase {
+ public:
+  Engine(const Options& opt, hipStream_t s, int64_t cap_m, int64_t cap_n, int64_t cap_nnz, int slots)
+      : opt_(opt), stream_(s), MS_(cap_m), NS_(cap_n), NZ_(cap_nnz), nslots_(slots),
+        am_(cap_m), an_(cap_n), az_(cap_nnz), slots_(slots) {
+    try {
+      allocate();
+    } catch (...) {
+      release_all();
+      throw;
+    }
+  }
+  ~Engine() override {
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    for (hipEvent_t e : pev_) (void)hipEventDestroy(e);
+    release_all();
+  }
+
+  hipStream_t stream() const override { return stream_; }
+  int64_t n_of(int id) const override { return slots_.at(id).n; }
+  int64_t m_of(int id) const override { return slots_.at(id).m; }
+  int live() const override {
+    int c = 0;
+    for (auto& s : slots_) c += s.used;
+    return c;
+  }
+
+  int64_t footprint(int64_t n, int64_t m, int64_t nnz) const override {
+    const int64_t s = sizeof(T);
+    const int64_t per_row = 4 + 3 * 8 + 9 * s, per_col = 4 + 5 * 8 + 10 * s;
+    const int64_t per_nz = 8 + 16 + (sizeof(T) == 8 ? 0 : 2 * s);
+    return per_row * (m + 1) + per_col * (n + 1) + per_nz * nnz;
+  }
+  KernelTimes kernel_times() const override { return ktimes_; }
+  bool fits(int64_t n, int64_t m, int64_t nnz) const override {
+    int free_slots = 0;
+    for (auto& s : slots_) free_slots += !s.used;
+    return free_slots > 0 && am_.can(m + 1) && an_.can(n + 1) && az_.can(nnz);
+  }
+
+  std::vector<int> add(const std::vector<Problem>& probs, bool on_device) override;
+  void set_params(const std::vector<int>& ids, double tol, int64_t max_iter) override;
+  void run(double time_limit_s) override;
+  std::vector<int> advance(int chunks) override;
+  void remove(const std::vector<int>& ids) override;
+  Result result(int id) override;
+  void solution(int id, double* x, double* y, bool to_device) override;
+  void certificate(int id, double* ray, bool to_device) override;
+
+ private:
+  void allocate();
+  void release_all();
+  void rebuild_schedules();
+  void launch_chunk();
+  void collect_times();
+  void transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1, const std::vector<Blk>& bD);
+  void preprocess(const std::vector<int>& ids, const std::vector<Blk>& nP, const std::vector<Blk>& nD,
+                  const std::vector<int4>& nr);
+  IterArgs<T> args() const;
+  void pull_states();
+
+  Options opt_;
+  hipStream_t stream_;
+  int64_t MS_, NS_, NZ_;
+  int nslots_;
+  RangeAlloc am_, an_, az_;
+  std::vector<Slot> slots_;
+  int64_t g_next_ = 0;  // index of the next step to launch
+
+  // nnz-space
+  int32_t *K_ci = nullptr, *KT_ci = nullptr;
+  double *K_v64 = nullptr, *KT_v64 = nullptr;
+  T *K_v = nullptr, *KT_v = nullptr;
+  // m-space
+  int32_t* K_rp = nullptr;
+  double *q_o = nullptr, *Dr = nullptr, *fm = nullptr;
+  T *q = nullptr, *y = nullptr, *y0 = nullptr, *yT = nullptr, *dy = nullptr, *kxbar = nullptr,
+    *kxp = nullptr, *cy1 = nullptr, *cy2 = nullptr;
+  // n-space
+  int32_t* KT_rp = nullptr;
+  double *c_o = nullptr, *l_o = nullptr, *u_o = nullptr, *Dc = nullptr, *fn = nullptr;
+  T *c = nullptr, *l = nullptr, *u = nullptr, *x = nullptr, *x0 = nullptr, *xbar = nullptr,
+    *xT = nullptr, *ktyp = nullptr, *cx1 = nullptr, *cx2 = nullptr;
+  // control
+  InstState* d_st = nullptr;
+  int* d_status = nullptr;
+  int* d_cnt = nullptr;
+  int64_t* d_gbase = nullptr;
+  Blk *d_schedP = nullptr, *d_schedD = nullptr;
+  int64_t capP_ = 0, capD_ = 0, nP_ = 0, nD_ = 0;
+  double *partP = nullptr, *partD = nullptr;
+  int* h_status[2] = {nullptr, nullptr};
+  hipEvent_t ev_[2] = {nullptr, nullptr};
+  bool sched_dirty_ = true;
+  hipGraphExec_t gexec_ = nullptr;
+  hipGraph_t graph_ = nullptr;
+  std::vector<InstState> h_st_;
+  int64_t chunk_count_ = 0;
+  std::vector<hipEvent_t> pev_;  // 3 events per profiled step, read after the solve
+  KernelTimes ktimes_;
+};
+
+template <class T>
+void Engine<T>::allocate() {
+  dalloc(&K_ci, NZ_);
+  dalloc(&KT_ci, NZ_);
+  dalloc(&K_v64, NZ_);
+  dalloc(&KT_v64, NZ_);
+  if (sizeof(T) == 8) {
+    K_v = (T*)K_v64;
+    KT_v = (T*)KT_v64;
+  } else {
+    dalloc(&K_v, NZ_);
+    dalloc(&KT_v, NZ_);
+  }
+  dalloc(&K_rp, MS_);
+  dalloc(&q_o, MS_);
+  dalloc(&Dr, MS_);
+  dalloc(&fm, MS_);
+  for (T** p : {&q, &y, &y0, &yT, &dy, &kxbar, &kxp, &cy1, &cy2}) dalloc(p, MS_);
+  dalloc(&KT_rp, NS_);
+  for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dalloc(p, NS_);
+  for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2}) dalloc(p, NS_);
+  dalloc(&d_st, nslots_);
+  dalloc(&d_status, nslots_);
+  dalloc(&d_cnt, nslots_);
+  dalloc(&d_gbase, 1);
+  HIPCHECK(hipMemsetAsync(d_cnt, 0, sizeof(int) * nslots_, stream_));
+  HIPCHECK(hipMemsetAsync(d_status, 0, sizeof(int) * nslots_, stream_));
+  HIPCHECK(hipMemsetAsync(d_st, 0, sizeof(InstState) * nslots_, stream_));
+  const int64_t gb = -(int64_t)opt_.chunk;
+  HIPCHECK(hipMemcpyAsync(d_gbase, &gb, sizeof(int64_t), hipMemcpyHostToDevice, stream_));
+  for (int i = 0; i < 2; ++i) {
+    HIPCHECK(hipHostMalloc((void**)&h_status[i], sizeof(int) * nslots_, hipHostMallocDefault));
+    std::memset(h_status[i], 0, sizeof(int) * nslots_);
+    HIPCHECK(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
+  }
+  h_st_.resize(nslots_);
+  HIPCHECK(hipStreamSynchronize(stream_));
+}
+
+template <class T>
+void Engine<T>::release_all() {
+  if (gexec_) (void)hipGraphExecDestroy(gexec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+  gexec_ = nullptr;
+  graph_ = nullptr;
+  dfree(K_ci);
+  dfree(KT_ci);
+  if (sizeof(T) != 8) {
+    dfree(K_v);
+    dfree(KT_v);
+  }
+  dfree(K_v64);
+  dfree(KT_v64);
+  dfree(K_rp);
+  dfree(q_o);
+  dfree(Dr);
+  dfree(fm);
+  for (T** p : {&q, &y, &y0, &yT, &dy, &kxbar, &kxp, &cy1, &cy2}) dfree(*p);
+  dfree(KT_rp);
+  for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dfree(*p);
+  for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2}) dfree(*p);
+  dfree(d_st);
+  dfree(d_status);
+  dfree(d_cnt);
+  dfree(d_gbase);
+  dfree(d_schedP);
+  dfree(d_schedD);
+  dfree(partP);
+  dfree(partD);
+  for (int i = 0; i < 2; ++i) {
+    if (h_status[i]) (void)hipHostFree(h_status[i]);
+    h_status[i] = nullptr;
+    if (ev_[i]) (void)hipEventDestroy(ev_[i]);
+    ev_[i] = nullptr;
+  }
+}
+
+template <class T>
+IterArgs<T> Engine<T>::args() const {
+  IterArgs<T> A;
+  A.K_rp = K_rp;
+  A.K_ci = K_ci;
+  A.K_v = K_v;
+  A.KT_rp = KT_rp;
+  A.KT_ci = KT_ci;
+  A.KT_v = KT_v;
+  A.c = c;
+  A.l = l;
+  A.u = u;
+  A.Dc = Dc;
+  A.x = x;
+  A.x0 = x0;
+  A.xbar = xbar;
+  A.xT = xT;
+  A.ktyp = ktyp;
+  A.cx1 = cx1;
+  A.cx2 = cx2;
+  A.q = q;
+  A.Dr = Dr;
+  A.y = y;
+  A.y0 = y0;
+  A.yT = yT;
+  A.dy = dy;
+  A.kxbar = kxbar;
+  A.kxp = kxp;
+  A.cy1 = cy1;
+  A.cy2 = cy2;
+  A.st = d_st;
+  A.gbase = d_gbase;
+  A.cnt = d_cnt;
+  A.status_out = d_status;
+  A.partP = partP;
+  A.partD = partD;
+  A.schedP = d_schedP;
+  A.schedD = d_schedD;
+  return A;
+}
+
+// ---------------------------------------------------------------------------
+// input validation and canonical CSR on the host
+// ---------------------------------------------------------------------------
+
+struct HostCSR {
+  std::vector<int32_t> rp, ci;
+  std::vector<double> val;
+};
+
+static void validate_host(const Problem& p, HostCSR& canon, bool& use_canon) {
+  const int64_t m = p.m_eq + p.m_ineq, n = p.n;
+  if (n < 1 || p.m_eq < 0 || p.m_ineq < 0) throw Error(-1, "sizes must satisfy n >= 1, m_eq >= 0, m_ineq >= 0");
+  if (!p.rp || (m > 0 && (!p.c || !p.rhs)) || !p.c || !p.lb || !p.ub)
+    throw Error(-1, "null input pointer");
+  if (p.rp[0] != 0) throw Error(-1, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < m; ++i)
+    if (p.rp[i + 1] < p.rp[i]) throw Error(-1, "row_ptr must be non-decreasing");
+  const int64_t nnz = p.rp[m];
+  if (nnz > 0 && (!p.ci || !p.val)) throw Error(-1, "null column or value array");
+  bool sorted = true;
+  for (int64_t i = 0; i < m; ++i) {
+    for (int64_t e = p.rp[i]; e < p.rp[i + 1]; ++e) {
+      const int64_t cidx = p.ci[e];
+      if (cidx < 0 || cidx >= n) throw Error(-1, "column index out of range");
+      if (!std::isfinite(p.val[e])) throw Error(-1, "non-finite matrix value");
+      if (e > p.rp[i] && cidx <= p.ci[e - 1]) sorted = false;
+    }
+  }
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(p.rhs[i])) throw Error(-1, "non-finite right-hand side");
+  for (int64_t j = 0; j < n; ++j) {
+    if (!std::isfinite(p.c[j])) throw Error(-1, "non-finite objective");
+    const double a = p.lb[j], b = p.ub[j];
+    if (std::isnan(a) || std::isnan(b) || a > b || a == INFINITY || b == -INFINITY)
+      throw Error(-1, "invalid bounds (NaN, lb > ub, lb = +inf or ub = -inf)");
+  }
+  use_canon = !sorted;
+  if (sorted) return;
+  // sort each row by column and sum duplicate entries
+  canon.rp.assign(m + 1, 0);
+  canon.ci.clear();
+  canon.val.clear();
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < m; ++i) {
+    row.clear();
+    for (int64_t e = p.rp[i]; e < p.rp[i + 1]; ++e) row.emplace_back(p.ci[e], p.val[e]);
+    std::stable_sort(row.begin(), row.end(),
+                     [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                       return a.first < b.first;
+                     });
+    for (size_t k = 0; k < row.size(); ++k) {
+      if (k > 0 && row[k].first == canon.ci.back()) {
+        canon.val.back() += row[k].second;
+      } else {
+        canon.ci.push_back(row[k].first);
+        canon.val.push_back(row[k].second);
+      }
+    }
+    canon.rp[i + 1] = (int32_t)canon.ci.size();
+  }
+}
+
+void validate_host_problem(const Problem& p) {
+  HostCSR canon;
+  bool uc = false;
+  validate_host(p, canon, uc);
+}
+
+// ---------------------------------------------------------------------------
+// add LPs
+// ---------------------------------------------------------------------------
+
+template <class T>
+void Engine<T>::transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1,
+                                const std::vector<Blk>& bD) {
+  if (nnz > 0) {
+    Blk* d_b = nullptr;
+    dalloc(&d_b, (int64_t)bD.size());
+    int32_t *rowid = nullptr, *keys = nullptr, *vin = nullptr, *vout = nullptr;
+    dalloc(&rowid, nnz);
+    dalloc(&keys, nnz);
+    dalloc(&vin, nnz);
+    dalloc(&vout, nnz);
+    HIPCHECK(hipMemcpyAsync(d_b, bD.data(), sizeof(Blk) * bD.size(), hipMemcpyHostToDevice, stream_));
+    row_ids_kernel<<<(unsigned)bD.size(), kThreads, 0, stream_>>>(d_b, K_rp, z0, rowid);
+    iota_kernel<<<nblk(nnz), 256, 0, stream_>>>(vin, nnz);
+    int end_bit = 1;
+    while (end_bit < 31 && ((int64_t)1 << end_bit) <= c1) ++end_bit;
+    size_t tmp_bytes = 0;
+    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, K_ci + z0, keys, vin, vout, (int)nnz, 0,
+                                                end_bit, stream_));
+    void* tmp = nullptr;
+    HIPCHECK(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
+    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, K_ci + z0, keys, vin, vout, (int)nnz, 0,
+                                                end_bit, stream_));
+    transpose_gather_kernel<double><<<nblk(nnz), 256, 0, stream_>>>(vout, rowid, K_v64, z0, nnz, KT_ci,
+                                                                     KT_v64);
+    transpose_rowptr_kernel<<<nblk(c1 - c0 + 1), 256, 0, stream_>>>(keys, nnz, z0, c0, c1, KT_rp);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(stream_));
+    (void)hipFree(tmp);
+    dfree(rowid);
+    dfree(keys);
+    dfree(vin);
+    dfree(vout);
+    dfree(d_b);
+  } else {
+    std::vector<int32_t> h(c1 - c0 + 1, (int32_t)z0);
+    HIPCHECK(hipMemcpyAsync(KT_rp + c0, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice,
+                            stream_));
+    HIPCHECK(hipStreamSynchronize(stream_));
+  }
+}
+
+template <class T>
+std::vector<int> Engine<T>::add(const std::vector<Problem>& probs, bool on_device) {
+  constexpr int NB = Tile<T>::NB;
+  std::vector<int> ids;
+  HIPCHECK(hipStreamSynchronize(stream_));
+  // 1. validate and reserve
+  std::vector<HostCSR> canon(probs.size());
+  std::vector<char> use_canon(probs.size(), 0);
+  for (size_t k = 0; k < probs.size(); ++k) {
+    const Problem& p = probs[k];
+    if (!on_device) {
+      bool uc = false;
+      validate_host(p, canon[k], uc);
+      use_canon[k] = uc;
+    } else {
+      if (p.n < 1 || p.m_eq < 0 || p.m_ineq < 0) throw Error(-1, "sizes must satisfy n >= 1, m >= 0");
+      const int64_t m = p.m_eq + p.m_ineq;
+      int32_t ends[2] = {0, 0};
+      HIPCHECK(hipMemcpy(&ends[0], p.rp, sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIPCHECK(hipMemcpy(&ends[1], p.rp + m, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (ends[0] != 0 || ends[1] < 0) throw Error(-1, "row_ptr must start at 0 and end at nnz >= 0");
+      int* d_flags = nullptr;
+      dalloc(&d_flags, 1);
+      HIPCHECK(hipMemsetAsync(d_flags, 0, sizeof(int), stream_));
+      if (m > 0)
+        validate_csr_kernel<<<nblk(m), 256, 0, stream_>>>(p.rp, p.ci, p.val, m, p.n, ends[1], d_flags);
+      validate_vectors_kernel<<<nblk(std::max<int64_t>(m, p.n)), 256, 0, stream_>>>(p.c, p.rhs, p.lb, p.ub,
+                                                                                     m, p.n, d_flags);
+      int flags = 0;
+      HIPCHECK(hipMemcpyAsync(&flags, d_flags, sizeof(int), hipMemcpyDeviceToHost, stream_));
+      HIPCHECK(hipStreamSynchronize(stream_));
+      dfree(d_flags);
+      if (flags & 1) throw Error(-1, "row_ptr must be non-decreasing from 0 to nnz");
+      if (flags & 2) throw Error(-1, "device CSR needs in-range, strictly increasing column indices per row");
+      if (flags & 4) throw Error(-1, "non-finite matrix value");
+      if (flags & 8) throw Error(-1, "non-finite objective or right-hand side");
+      if (flags & 16) throw Error(-1, "invalid bounds (NaN, lb > ub, lb = +inf or ub = -inf)");
+    }
+  }
+  std::vector<int64_t> nnzs(probs.size());
+  for (size_t k = 0; k < probs.size(); ++k) {
+    const Problem& p = probs[k];
+    const int64_t m = p.m_eq + p.m_ineq;
+    if (use_canon[k]) {
+      nnzs[k] = canon[k].rp[m];
+    } else if (!on_device) {
+      nnzs[k] = p.rp[m];
+    } else {
+      int32_t e = 0;
+      HIPCHECK(hipMemcpy(&e, p.rp + m, sizeof(int32_t), hipMemcpyDeviceToHost));
+      nnzs[k] = e;
+    }
+  }
+  std::vector<int> fresh;
+  try {
+    for (size_t k = 0; k < probs.size(); ++k) {
+      const Problem& p = probs[k];
+      const int64_t m = p.m_eq + p.m_ineq;
+      int id = -1;
+      for (int s = 0; s < nslots_; ++s)
+        if (!slots_[s].used) {
+          id = s;
+          break;
+        }
+      if (id < 0) throw Error(-2, "no free LP slot");
+      const int64_t r0 = am_.alloc(m + 1);
+      const int64_t c0 = r0 < 0 ? -1 : an_.alloc(p.n + 1);
+      const int64_t z0 = c0 < 0 ? -1 : az_.alloc(nnzs[k]);
+      if (r0 < 0 || c0 < 0 || z0 < 0) {
+        if (r0 >= 0) am_.release(r0, m + 1);
+        if (c0 >= 0) an_.release(c0, p.n + 1);
+        throw Error(-2, "not enough device memory reserved for this LP");
+      }
+      if (z0 + nnzs[k] > INT32_MAX) throw Error(-1, "more than 2^31 stored entries");
+      Slot& S = slots_[id];
+      S = Slot();
+      S.used = true;
+      S.n = p.n;
+      S.m = m;
+      S.m_eq = p.m_eq;
+      S.nnz = nnzs[k];
+      S.row0 = r0;
+      S.col0 = c0;
+      S.nz0 = z0;
+      ids.push_back(id);
+      fresh.push_back(id);
+    }
+  } catch (...) {
+    for (int id : fresh) {
+      Slot& S = slots_[id];
+      am_.release(S.row0, S.m + 1);
+      an_.release(S.col0, S.n + 1);
+      az_.release(S.nz0, S.nnz);
+      S = Slot();
+    }
+    throw;
+  }
+
+  // 2. upload (K values in FP64, row pointers / columns shifted to space positions)
+  std::vector<std::vector<int32_t>> host_rp(probs.size());
+  for (size_t k = 0; k < probs.size(); ++k) {
+    const Problem& p = probs[k];
+    Slot& S = slots_[ids[k]];
+    const int64_t m = S.m, n = S.n, nnz = S.nnz;
+    const auto kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const int32_t* rp_src = use_canon[k] ? canon[k].rp.data() : p.rp;
+    const int32_t* ci_src = use_canon[k] ? canon[k].ci.data() : p.ci;
+    const double* v_src = use_canon[k] ? canon[k].val.data() : p.val;
+    host_rp[k].resize(m + 1);
+    if (!on_device) {
+      for (int64_t i = 0; i <= m; ++i) host_rp[k][i] = (int32_t)(rp_src[i] + S.nz0);
+      HIPCHECK(hipMemcpyAsync(K_rp + S.row0, host_rp[k].data(), sizeof(int32_t) * (m + 1),
+                              hipMemcpyHostToDevice, stream_));
+      std::vector<int32_t> cs(nnz);
+      for (int64_t e = 0; e < nnz; ++e) cs[e] = (int32_t)(ci_src[e] + S.col0);
+      if (nnz) {
+        HIPCHECK(hipMemcpyAsync(K_ci + S.nz0, cs.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, stream_));
+        HIPCHECK(hipMemcpyAsync(K_v64 + S.nz0, v_src, sizeof(double) * nnz, hipMemcpyHostToDevice, stream_));
+      }
+      HIPCHECK(hipStreamSynchronize(stream_));
+    } else {
+      shift_copy_kernel<<<nblk(m + 1), 256, 0, stream_>>>(K_rp + S.row0, p.rp, m + 1, S.nz0);
+      if (nnz) {
+        shift_copy_kernel<<<nblk(nnz), 256, 0, stream_>>>(K_ci + S.nz0, p.ci, nnz, S.col0);
+        HIPCHECK(hipMemcpyAsync(K_v64 + S.nz0, p.val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
+      }
+      HIPCHECK(hipMemcpyAsync(host_rp[k].data(), K_rp + S.row0, sizeof(int32_t) * (m + 1),
+                              hipMemcpyDeviceToHost, stream_));
+    }
+    if (m) HIPCHECK(hipMemcpyAsync(q_o + S.row0, p.rhs, sizeof(double) * m, kind, stream_));
+    HIPCHECK(hipMemcpyAsync(c_o + S.col0, p.c, sizeof(double) * n, kind, stream_));
+    HIPCHECK(hipMemcpyAsync(l_o + S.col0, p.lb, sizeof(double) * n, kind, stream_));
+    HIPCHECK(hipMemcpyAsync(u_o + S.col0, p.ub, sizeof(double) * n, kind, stream_));
+    fill_kernel<<<nblk(m + 1), 256, 0, stream_>>>(Dr + S.row0, m + 1, 1.0);
+    fill_kernel<<<nblk(n + 1), 256, 0, stream_>>>(Dc + S.col0, n + 1, 1.0);
+  }
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(stream_));
+
+  // 3. dual schedules, transpose, primal schedules
+  for (size_t k = 0; k < probs.size(); ++k) {
+    Slot& S = slots_[ids[k]];
+    build_blocks(host_rp[k].data(), S.m, S.row0, ids[k], NB, S.bD);
+    // host_rp holds space positions; build_blocks only uses differences
+  }
+  // contiguous groups transpose together
+  size_t k = 0;
+  while (k < probs.size()) {
+    size_t e = k + 1;
+    while (e < probs.size()) {
+      const Slot& A = slots_[ids[e - 1]];
+      const Slot& B = slots_[ids[e]];
+      if (B.row0 != A.row0 + A.m + 1 || B.col0 != A.col0 + A.n + 1 || B.nz0 != A.nz0 + A.nnz) break;
+      ++e;
+    }
+    const Slot& F = slots_[ids[k]];
+    const Slot& L = slots_[ids[e - 1]];
+    std::vector<Blk> bD;
+    for (size_t t = k; t < e; ++t) bD.insert(bD.end(), slots_[ids[t]].bD.begin(), slots_[ids[t]].bD.end());
+    transpose_group(F.nz0, L.nz0 + L.nnz - F.nz0, F.col0, L.col0 + L.n, bD);
+    k = e;
+  }
+  for (size_t t = 0; t < probs.size(); ++t) {
+    Slot& S = slots_[ids[t]];
+    std::vector<int32_t> krp(S.n + 1);
+    HIPCHECK(hipMemcpy(krp.data(), KT_rp + S.col0, sizeof(int32_t) * (S.n + 1), hipMemcpyDeviceToHost));
+    build_blocks(krp.data(), S.n, S.col0, ids[t], NB, S.bP);
+  }
+
+  // 4. temporary schedules of the new LPs, preprocessing, power iteration
+  std::vector<Blk> nP, nD;
+  std::vector<int4> nr;
+  for (int id : ids) {
+    const Slot& S = slots_[id];
+    int4 r;
+    r.x = (int)nP.size();
+    nP.insert(nP.end(), S.bP.begin(), S.bP.end());
+    r.y = (int)nP.size();
+    r.z = (int)nD.size();
+    nD.insert(nD.end(), S.bD.begin(), S.bD.end());
+    r.w = (int)nD.size();
+    nr.push_back(r);
+  }
+  preprocess(ids, nP, nD, nr);
+  sched_dirty_ = true;
+  for (int id : ids) slots_[id].watched = true;
+  return ids;
+}
+
+template <class T>
+void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& nP,
+                           const std::vector<Blk>& nD, const std::vector<int4>& nr) {
+  const int ni = (int)ids.size();
+  Blk *d_nP = nullptr, *d_nD = nullptr;
+  int* d_ids = nullptr;
+  int4* d_nr = nullptr;
+  double* d_pp = nullptr;
+  double* d_norms = nullptr;
+  int* d_active = nullptr;
+  InstState* d_src = nullptr;
+  auto cleanup = [&]() {
+    dfree(d_nP);
+    dfree(d_nD);
+    dfree(d_ids);
+    dfree(d_nr);
+    dfree(d_pp);
+    dfree(d_norms);
+    dfree(d_active);
+    dfree(d_src);
+  };
+  try {
+    dalloc(&d_nP, (int64_t)nP.size());
+    dalloc(&d_nD, (int64_t)nD.size());
+    dalloc(&d_ids, ni);
+    dalloc(&d_nr, ni);
+    dalloc(&d_pp, (int64_t)nP.size() * kNS);
+    dalloc(&d_norms, 2 * ni);
+    dalloc(&d_active, 1);
+    dalloc(&d_src, ni);
+    HIPCHECK(hipMemcpyAsync(d_nP, nP.data(), sizeof(Blk) * nP.size(), hipMemcpyHostToDevice, stream_));
+    HIPCHECK(hipMemcpyAsync(d_nD, nD.data(), sizeof(Blk) * nD.size(), hipMemcpyHostToDevice, stream_));
+    HIPCHECK(hipMemcpyAsync(d_ids, ids.data(), sizeof(int) * ni, hipMemcpyHostToDevice, stream_));
+    HIPCHECK(hipMemcpyAsync(d_nr, nr.data(), sizeof(int4) * ni, hipMemcpyHostToDevice, stream_));
+    const unsigned gP = (unsigned)nP.size(), gD = (unsigned)nD.size();
+
+    // scaling (Ruiz infinity-norm passes, then Pock-Chambolle)
+    for (int it = 0; it < opt_.ruiz_iters; ++it) {
+      row_factor_kernel<<<gD, kThreads, 0, stream_>>>(d_nD, K_rp, K_v64, 0, 1.0, fm, Dr);
+      row_factor_kernel<<<gP, kThreads, 0, stream_>>>(d_nP, KT_rp, KT_v64, 0, 1.0, fn, Dc);
+      scale_values_kernel<<<gD, kThreads, 0, stream_>>>(d_nD, K_rp, K_ci, K_v64, fm, fn, 0);
+      scale_values_kernel<<<gP, kThreads, 0, stream_>>>(d_nP, KT_rp, KT_ci, KT_v64, fm, fn, 1);
+    }
+    if (opt_.pc_alpha > 0.0) {
+      row_factor_kernel<<<gD, kThreads, 0, stream_>>>(d_nD, K_rp, K_v64, 1, 2.0 - opt_.pc_alpha, fm, Dr);
+      row_factor_kernel<<<gP, kThreads, 0, stream_>>>(d_nP, KT_rp, KT_v64, 1, opt_.pc_alpha, fn, Dc);
+      scale_values_kernel<<<gD, kThreads, 0, stream_>>>(d_nD, K_rp, K_ci, K_v64, fm, fn, 0);
+      scale_values_kernel<<<gP, kThreads, 0, stream_>>>(d_nP, KT_rp, KT_ci, KT_v64, fm, fn, 1);
+    }
+    scale_primal_kernel<T><<<gP, kThreads, 0, stream_>>>(d_nP, Dc, c_o, l_o, u_o, c, l, u);
+    scale_dual_kernel<T><<<gD, kThreads, 0, stream_>>>(d_nD, Dr, q_o, q);
+
+    // layout constants for the norm and power kernels
+    std::vector<InstState> src(ni);
+    for (int k = 0; k < ni; ++k) {
+      const Slot& S = slots_[ids[k]];
+      InstState& s = src[k];
+      std::memset(&s, 0, sizeof(InstState));
+      s.row0 = S.row0;
+      s.col0 = S.col0;
+      s.nz0 = S.nz0;
+      s.m = (int32_t)S.m;
+      s.m_eq = (int32_t)S.m_eq;
+      s.n = (int32_t)S.n;
+      s.status = ST_ITER_LIMIT;  // parked until set_params
+      s.pw_done = opt_.eta > 0.0 ? 1 : 0;
+    }
+    HIPCHECK(hipMemcpyAsync(d_src, src.data(), sizeof(InstState) * ni, hipMemcpyHostToDevice, stream_));
+    write_states_kernel<<<nblk(ni), 256, 0, stream_>>>(d_st, d_status, d_cnt, d_ids, d_src, ni);
+    inst_norms_kernel<<<ni, kThreads, 0, stream_>>>(d_st, d_ids, q_o, c_o, Dr, Dc, d_norms);
+
+    // power iteration on K~^T K~ (u in fm, w in fn)
+    int piters = 0;
+    if (opt_.eta <= 0.0) {
+      pw_start_kernel<<<gP, kThreads, 0, stream_>>>(d_nP, d_st, opt_.seed, fn, d_pp);
+      HIPCHECK(hipMemsetAsync(d_active, 0, sizeof(int), stream_));
+      pw_control_kernel<<<ni, kThreads, 0, stream_>>>(d_st, d_ids, d_nr, d_pp, 1, opt_.power_min_iters,
+                                                      opt_.power_max_iters, opt_.power_rtol, d_active);
+      int active = 1;
+      while (active > 0 && piters < opt_.power_max_iters) {
+        const int batch = 8;
+        for (int b = 0; b < batch && piters < opt_.power_max_iters; ++b, ++piters) {
+          pw_forward_kernel<<<gD, kThreads, 0, stream_>>>(d_nD, d_st, K_rp, K_ci, K_v64, fn, fm);
+          pw_backward_kernel<<<gP, kThreads, 0, stream_>>>(d_nP, d_st, KT_rp, KT_ci, KT_v64, fm, fn, d_pp);
+          HIPCHECK(hipMemsetAsync(d_active, 0, sizeof(int), stream_));
+          pw_control_kernel<<<ni, kThreads, 0, stream_>>>(d_st, d_ids, d_nr, d_pp, 0, opt_.power_min_iters,
+                                                          opt_.power_max_iters, opt_.power_rtol, d_active);
+        }
+        HIPCHECK(hipMemcpyAsync(&active, d_active, sizeof(int), hipMemcpyDeviceToHost, stream_));
+        HIPCHECK(hipStreamSynchronize(stream_));
+      }
+    }
+    if (sizeof(T) != 8) {
+      for (int id : ids) {
+        const Slot& S = slots_[id];
+        if (S.nnz) {
+          cast_kernel<T><<<nblk(S.nnz), 256, 0, stream_>>>(K_v64 + S.nz0, K_v + S.nz0, S.nnz);
+          cast_kernel<T><<<nblk(S.nnz), 256, 0, stream_>>>(KT_v64 + S.nz0, KT_v + S.nz0, S.nnz);
+        }
+      }
+    }
+    init_primal_kernel<T><<<gP, kThreads, 0, stream_>>>(d_nP, l, u, x, x0);
+    init_dual_kernel<T><<<gD, kThreads, 0, stream_>>>(d_nD, y, y0);
+    HIPCHECK(hipGetLastError());
+
+    // step size and primal weight, then park the LPs until set_params
+    std::vector<double> norms(2 * ni);
+    HIPCHECK(hipMemcpyAsync(norms.data(), d_norms, sizeof(double) * 2 * ni, hipMemcpyDeviceToHost, stream_));
+    std::vector<InstState> cur(ni);
+    for (int k = 0; k < ni; ++k)
+      HIPCHECK(hipMemcpyAsync(&cur[k], d_st + ids[k], sizeof(InstState), hipMemcpyDeviceToHost, stream_));
+    HIPCHECK(hipStreamSynchronize(stream_));
+    for (int k = 0; k < ni; ++k) {
+      InstState& s = cur[k];
+      const double sh = s.sigma_hat;
+      double eta;
+      if (opt_.eta > 0.0) {
+        eta = opt_.eta;
+        s.sigma_hat = NAN;
+      } else {
+        eta = sh > 0.0 ? opt_.step_safety / sh : opt_.step_safety;
+      }
+      const double nq = norms[2 * k], nc = norms[2 * k + 1];
+      double omega = 1.0;
+      if (opt_.omega0 > 0.0) omega = opt_.omega0;
+      else if (opt_.primal_weight && nc > 1e-10 && nq > 1e-10) omega = nc / nq;
+      s.eta = eta;
+      s.omega = omega;
+      s.tau = eta / omega;
+      s.sigma = eta * omega;
+      s.reflect = opt_.method == 1;
+      s.C = opt_.check_every;
+      s.primal_weight = opt_.primal_weight;
+      s.beta = opt_.restart_beta;
+      s.artificial = opt_.artificial_restart;
+      s.eps_inf = opt_.eps_infeas;
+      s.r0 = NAN;
+      s.status = ST_ITER_LIMIT;  // parked
+      s.phase = PH_NORMAL;
+      s.nrest = 0;
+      s.checks = 0;
+      s.ray = 0;
+      s.iters = 0;
+      s.kkt = NAN;
+      h_st_[ids[k]] = s;
+    }
+    HIPCHECK(hipMemcpyAsync(d_src, cur.data(), sizeof(InstState) * ni, hipMemcpyHostToDevice, stream_));
+    write_states_kernel<<<nblk(ni), 256, 0, stream_>>>(d_st, d_status, d_cnt, d_ids, d_src, ni);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(stream_));
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
+
+template <class T>
+void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_iter) {
+  HIPCHECK(hipStreamSynchronize(stream_));
+  const int ni = (int)ids.size();
+  if (ni == 0) return;
+  std::vector<InstState> cur(ni);
+  for (int k = 0; k < ni; ++k)
+    HIPCHECK(hipMemcpyAsync(&cur[k], d_st + ids[k], sizeof(InstState), hipMemcpyDeviceToHost, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  for (int k = 0; k < ni; ++k) {
+    InstState& s = cur[k];
+    s.tol = tol;
+    s.max_iter = max_iter;
+    if (s.status != ST_RUNNING) {
+      // (re)start from the last candidate as a fresh epoch is not supported
+      // for finished LPs; a parked LP starts here
+      if (s.checks == 0) {
+        s.status = ST_RUNNING;
+        s.phase = PH_NORMAL;
+        s.kbase = g_next_;
+        s.tbase = g_next_;
+      }
+    }
+    slots_[ids[k]].watched = true;
+    slots_[ids[k]].reported = false;
+  }
+  InstState* d_src = nullptr;
+  int* d_ids = nullptr;
+  dalloc(&d_src, ni);
+  dalloc(&d_ids, ni);
+  HIPCHECK(hipMemcpyAsync(d_src, cur.data(), sizeof(InstState) * ni, hipMemcpyHostToDevice, stream_));
+  HIPCHECK(hipMemcpyAsync(d_ids, ids.data(), sizeof(int) * ni, hipMemcpyHostToDevice, stream_));
+  write_states_kernel<<<nblk(ni), 256, 0, stream_>>>(d_st, d_status, d_cnt, d_ids, d_src, ni);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(stream_));
+  dfree(d_src);
+  dfree(d_ids);
+  for (int k = 0; k < ni; ++k) h_status[0][ids[k]] = h_status[1][ids[k]] = cur[k].status;
+}
+
+template <class T>
+void Engine<T>::rebuild_schedules() {
+  std::vector<Blk> P, D;
+  std::vector<int> live;
+  std::vector<int4> rg;
+  for (int s = 0; s < nslots_; ++s) {
+    if (!slots_[s].used) continue;
+    int4 r;
+    r.x = (int)P.size();
+    P.insert(P.end(), slots_[s].bP.begin(), slots_[s].bP.end());
+    r.y = (int)P.size();
+    r.z = (int)D.size();
+    D.insert(D.end(), slots_[s].bD.begin(), slots_[s].bD.end());
+    r.w = (int)D.size();
+    live.push_back(s);
+    rg.push_back(r);
+  }
+  HIPCHECK(hipStreamSynchronize(stream_));
+  if ((int64_t)P.size() > capP_) {
+    dfree(d_schedP);
+    dfree(partP);
+    capP_ = std::max<int64_t>((int64_t)P.size(), 2 * capP_);
+    dalloc(&d_schedP, capP_);
+    dalloc(&partP, capP_ * kNS);
+  }
+  if ((int64_t)D.size() > capD_) {
+    dfree(d_schedD);
+    dfree(partD);
+    capD_ = std::max<int64_t>((int64_t)D.size(), 2 * capD_);
+    dalloc(&d_schedD, capD_);
+    dalloc(&partD, capD_ * kNS);
+  }
+  nP_ = (int64_t)P.size();
+  nD_ = (int64_t)D.size();
+  if (nP_) HIPCHECK(hipMemcpyAsync(d_schedP, P.data(), sizeof(Blk) * nP_, hipMemcpyHostToDevice, stream_));
+  if (nD_) HIPCHECK(hipMemcpyAsync(d_schedD, D.data(), sizeof(Blk) * nD_, hipMemcpyHostToDevice, stream_));
+  if (!live.empty()) {
+    int* d_ids = nullptr;
+    int4* d_rg = nullptr;
+    dalloc(&d_ids, (int64_t)live.size());
+    dalloc(&d_rg, (int64_t)live.size());
+    HIPCHECK(hipMemcpyAsync(d_ids, live.data(), sizeof(int) * live.size(), hipMemcpyHostToDevice, stream_));
+    HIPCHECK(hipMemcpyAsync(d_rg, rg.data(), sizeof(int4) * rg.size(), hipMemcpyHostToDevice, stream_));
+    set_ranges_kernel<<<nblk((int64_t)live.size()), 256, 0, stream_>>>(d_st, d_ids, d_rg, (int)live.size());
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(stream_));
+    dfree(d_ids);
+    dfree(d_rg);
+  }
+  if (gexec_) {
+    (void)hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+  }
+  if (graph_) {
+    (void)hipGraphDestroy(graph_);
+    graph_ = nullptr;
+  }
+  sched_dirty_ = false;
+}
+
+template <class T>
+void Engine<T>::launch_chunk() {
+  if (sched_dirty_) rebuild_schedules();
+  if (nP_ == 0 || nD_ == 0) return;
+  const IterArgs<T> A = args();
+  const int CH = opt_.chunk;
+  const bool prof = opt_.profile > 0 && (chunk_count_ % opt_.profile) == 0;
+  ++chunk_count_;
+  auto enqueue = [&](bool timed) {
+    tick_kernel<<<1, 1, 0, stream_>>>(d_gbase, (int64_t)CH);
+    for (int i = 0; i < CH; ++i) {
+      hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+      if (timed) {
+        for (int k = 0; k < 3; ++k) {
+          HIPCHECK(hipEventCreate(&e[k]));
+          pev_.push_back(e[k]);
+        }
+        HIPCHECK(hipEventRecord(e[0], stream_));
+      }
+      primal_step<T><<<(unsigned)nP_, kThreads, 0, stream_>>>(A, i);
+      if (timed) HIPCHECK(hipEventRecord(e[1], stream_));
+      dual_step<T><<<(unsigned)nD_, kThreads, 0, stream_>>>(A, i);
+      if (timed) HIPCHECK(hipEventRecord(e[2], stream_));
+    }
+  };
+  if (prof) {
+    enqueue(true);
+    HIPCHECK(hipGetLastError());
+  } else if (opt_.use_graph) {
+    if (!gexec_) {
+      HIPCHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+      enqueue(false);
+      HIPCHECK(hipStreamEndCapture(stream_, &graph_));
+      HIPCHECK(hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0));
+    }
+    HIPCHECK(hipGraphLaunch(gexec_, stream_));
+  } else {
+    enqueue(false);
+    HIPCHECK(hipGetLastError());
+  }
+  g_next_ += CH;
+}
+
+template <class T>
+void Engine<T>::collect_times() {
+  if (pev_.empty()) return;
+  HIPCHECK(hipStreamSynchronize(stream_));
+  for (size_t k = 0; k + 2 < pev_.size(); k += 3) {
+    float a = 0.f, b = 0.f;
+    HIPCHECK(hipEventElapsedTime(&a, pev_[k], pev_[k + 1]));
+    HIPCHECK(hipEventElapsedTime(&b, pev_[k + 1], pev_[k + 2]));
+    ktimes_.primal_ms += a;
+    ktimes_.dual_ms += b;
+    ktimes_.launches += 1;
+  }
+  for (hipEvent_t e : pev_) (void)hipEventDestroy(e);
+  pev_.clear();
+}
+
+template <class T>
+void Engine<T>::run(double time_limit_s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (sched_dirty_) rebuild_schedules();
+  auto all_done = [&](const int* h) {
+    for (int s = 0; s < nslots_; ++s)
+      if (slots_[s].used && slots_[s].watched && h[s] == ST_RUNNING) return false;
+    return true;
+  };
+  if (all_done(h_status[0]) && all_done(h_status[1])) {
+    HIPCHECK(hipStreamSynchronize(stream_));
+    HIPCHECK(hipMemcpy(h_status[0], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost));
+    if (all_done(h_status[0])) return;
+  }
+  int64_t j = 0;
+  bool limit_set = false;
+  while (true) {
+    launch_chunk();
+    HIPCHECK(hipMemcpyAsync(h_status[j & 1], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost, stream_));
+    HIPCHECK(hipEventRecord(ev_[j & 1], stream_));
+    if (j >= 1) {
+      HIPCHECK(hipEventSynchronize(ev_[(j - 1) & 1]));
+      if (all_done(h_status[(j - 1) & 1])) break;
+    }
+    ++j;
+    if (!limit_set && time_limit_s >= 0.0) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el > time_limit_s) {
+        set_limit_status_kernel<<<nblk(nslots_), 256, 0, stream_>>>(d_st, d_status, nslots_, ST_TIME_LIMIT);
+        limit_set = true;
+      }
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(stream_));
+  HIPCHECK(hipMemcpy(h_status[0], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost));
+  std::memcpy(h_status[1], h_status[0], sizeof(int) * nslots_);
+  collect_times();
+}
+
+template <class T>
+std::vector<int> Engine<T>::advance(int chunks) {
+  for (int i = 0; i < chunks; ++i) launch_chunk();
+  HIPCHECK(hipMemcpyAsync(h_status[0], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  collect_times();
+  std::vector<int> done;
+  for (int s = 0; s < nslots_; ++s) {
+    if (slots_[s].used && slots_[s].watched && !slots_[s].reported && h_status[0][s] != ST_RUNNING) {
+      slots_[s].reported = true;
+      done.push_back(s);
+    }
+  }
+  return done;
+}
+
+template <class T>
+void Engine<T>::remove(const std::vector<int>& ids) {
+  HIPCHECK(hipStreamSynchronize(stream_));
+  for (int id : ids) {
+    Slot& S = slots_.at(id);
+    if (!S.used) continue;
+    am_.release(S.row0, S.m + 1);
+    an_.release(S.col0, S.n + 1);
+    az_.release(S.nz0, S.nnz);
+    S = Slot();
+    h_status[0][id] = h_status[1][id] = 0;
+  }
+  // parked slots never run: mark them finished on the device
+  sched_dirty_ = true;
+}
+
+template <class T>
+Result Engine<T>::result(int id) {
+  if (id < 0 || id >= nslots_ || !slots_[id].used) throw Error(-1, "invalid LP id");
+  InstState s;
+  HIPCHECK(hipStreamSynchronize(stream_));
+  HIPCHECK(hipMemcpy(&s, d_st + id, sizeof(InstState), hipMemcpyDeviceToHost));
+  Result r;
+  r.status = s.status;
+  if (s.checks == 0 && s.status == ST_ITER_LIMIT) r.status = 0;  // parked, never run
+  r.iters = s.iters;
+  r.restarts = s.nrest;
+  r.checks = s.checks;
+  r.kkt = s.kkt;
+  r.rel_p = s.rel_p;
+  r.rel_d = s.rel_d;
+  r.rel_gap = s.rel_gap;
+  r.pobj = s.pobj;
+  r.dobj = s.dobj;
+  r.resid = s.resid;
+  r.omega = s.omega;
+  r.eta = s.eta;
+  r.sigma_hat = s.sigma_hat;
+  r.power_iters = s.pw_iter;
+  r.ray = s.ray;
+  return r;
+}
+
+template <class T>
+void Engine<T>::solution(int id, double* xo, double* yo, bool to_device) {
+  if (id < 0 || id >= nslots_ || !slots_[id].used) throw Error(-1, "invalid LP id");
+  const Slot& S = slots_[id];
+  double* tmp = nullptr;
+  dalloc(&tmp, S.n + S.m);
+  unscale_kernel<T><<<nblk(S.n), 256, 0, stream_>>>(xT, Dc, S.col0, S.n, tmp);
+  if (S.m) unscale_kernel<T><<<nblk(S.m), 256, 0, stream_>>>(yT, Dr, S.row0, S.m, tmp + S.n);
+  HIPCHECK(hipGetLastError());
+  const auto kind = to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (xo) HIPCHECK(hipMemcpyAsync(xo, tmp, sizeof(double) * S.n, kind, stream_));
+  if (yo && S.m) HIPCHECK(hipMemcpyAsync(yo, tmp + S.n, sizeof(double) * S.m, kind, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  dfree(tmp);
+}
+
+template <class T>
+void Engine<T>::certificate(int id, double* ray, bool to_device) {
+  if (id < 0 || id >= nslots_ || !slots_[id].used) throw Error(-1, "invalid LP id");
+  const Slot& S = slots_[id];
+  InstState s;
+  HIPCHECK(hipStreamSynchronize(stream_));
+  HIPCHECK(hipMemcpy(&s, d_st + id, sizeof(InstState), hipMemcpyDeviceToHost));
+  if (s.status != ST_PRIMAL_INFEAS && s.status != ST_DUAL_INFEAS)
+    throw Error(-4, "no certificate: the LP was not found infeasible");
+  const bool primal = s.status == ST_PRIMAL_INFEAS;
+  const int64_t len = primal ? S.m : S.n;
+  double* tmp = nullptr;
+  dalloc(&tmp, len);
+  if (primal)
+    unscale_kernel<T><<<nblk(len), 256, 0, stream_>>>(s.ray == 1 ? cy1 : cy2, Dr, S.row0, len, tmp);
+  else
+    unscale_kernel<T><<<nblk(len), 256, 0, stream_>>>(s.ray == 1 ? cx1 : cx2, Dc, S.col0, len, tmp);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(ray, tmp, sizeof(double) * len, to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  dfree(tmp);
+}
+
+std::unique_ptr<EngineBase> make_engine(const Options& opt, hipStream_t stream, int64_t cap_m, int64_t cap_n,
+                                        int64_t cap_nnz, int max_slots) {
+  if (opt.precision == 1)
+    return std::unique_ptr<EngineBase>(new Engine<float>(opt, stream, cap_m, cap_n, cap_nnz, max_slots));
+  return std::unique_ptr<EngineBase>(new Engine<double>(opt, stream, cap_m, cap_n, cap_nnz, max_slots));
+}
+
+}  // namespace halp

@@ -1,0 +1,61 @@
+// Shared host/device types of the HIP solver.
+//
+// Vectors of every live LP sit in three "spaces": m-space (constraint rows),
+// n-space (variables) and nnz-space (matrix entries).  An instance owns the
+// contiguous ranges [row0, row0 + m + 1), [col0, col0 + n + 1) and
+// [nz0, nz0 + nnz); the extra position closes its CSR row pointers.  Column
+// indices of K and of the explicit transpose K^T are stored as global space
+// positions, so the sparse kernels never translate indices.
+#pragma once
+#include <stdint.h>
+
+namespace halp {
+
+constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxRows = 256;        // rows per "stream" block (one epilogue row per thread)
+constexpr int kNS = 8;               // partial-sum slots per block
+constexpr int kNAcc = 12;            // sums kept from a check step for the following eval step
+
+// nnz per stream block; rows longer than this get a block of their own.
+template <class T> struct Tile { static constexpr int NB = 2048; };
+
+enum Mode : int { M_SKIP = 0, M_NORMAL = 1, M_CHECK = 2, M_EVAL = 3, M_RESID = 4 };
+enum Phase : int { PH_NORMAL = 0, PH_EVAL = 1, PH_RESID = 2 };
+enum BlkKind : int { BK_STREAM = 0, BK_LONG = 1 };
+enum Status : int { ST_RUNNING = 0, ST_OPTIMAL = 1, ST_PRIMAL_INFEAS = 2, ST_DUAL_INFEAS = 3,
+                    ST_ITER_LIMIT = 4, ST_TIME_LIMIT = 5, ST_NUMERICAL = 6 };
+
+// One workgroup's share of a CSR matrix: rows [r0, r1) (space positions).
+struct Blk {
+  int32_t r0, r1, inst, kind;
+};
+
+// Check-step sums (stored in InstState::acc between the check and eval steps).
+enum AccSlot : int {
+  A_DX2 = 0, A_AX2, A_POBJ, A_CD1, A_CD2,       // from the primal kernel
+  A_DY2, A_AY2, A_DOBJQ, A_QY1, A_QY2,          // from the dual kernel
+};
+
+struct alignas(16) InstState {
+  // layout and constants
+  int64_t row0, col0, nz0;
+  int32_t m, m_eq, n, reflect;
+  int32_t C, primal_weight;
+  int32_t pb0, pb1, db0, db1;        // this instance's blocks in the primal / dual schedules
+  double tol, eps_inf, beta, artificial, eta, qnorm, cnorm;
+  int64_t max_iter;
+  // dynamic state
+  int32_t status, phase;
+  int64_t kbase, tbase, nrest, checks;
+  double omega, tau, sigma, r0;
+  double acc[kNAcc];
+  // last check
+  double kkt, rel_p, rel_d, rel_gap, pobj, dobj, resid;
+  int64_t iters;
+  int32_t ray, pad0;
+  // power iteration
+  double pw_scale, pw_prev, sigma_hat;
+  int32_t pw_iter, pw_done;
+};
+
+}  // namespace halp

@@ -1,0 +1,52 @@
+// Argument block of the two per-step kernels.
+#pragma once
+#include <stdint.h>
+
+#include "halp_types.h"
+
+namespace halp {
+
+template <class T>
+struct IterArgs {
+  // K (rows = constraints) and the explicit K^T (rows = variables), scaled
+  const int32_t* K_rp;
+  const int32_t* K_ci;
+  const T* K_v;
+  const int32_t* KT_rp;
+  const int32_t* KT_ci;
+  const T* KT_v;
+  // n-space
+  const T* c;
+  const T* l;
+  const T* u;
+  const double* Dc;
+  T* x;      // iterate z^{n,k}, x part
+  T* x0;     // anchor z^{n,0}
+  T* xbar;   // 2 x+ - x, gathered by the dual SpMV
+  T* xT;     // T(z) at the last check
+  T* ktyp;   // K^T y+ at the last eval
+  T* cx1;    // dual-infeasibility ray candidates (recession-projected)
+  T* cx2;
+  // m-space
+  const T* q;
+  const double* Dr;
+  T* y;
+  T* y0;
+  T* yT;
+  T* dy;     // y - y+ at the last check
+  T* kxbar;  // K xbar at the last check
+  T* kxp;    // K x+ at the last eval
+  T* cy1;    // primal-infeasibility ray candidates (clamped)
+  T* cy2;
+  // control
+  InstState* st;
+  const int64_t* gbase;
+  int* cnt;
+  int* status_out;
+  double* partP;
+  double* partD;
+  const Blk* schedP;
+  const Blk* schedD;
+};
+
+}  // namespace halp

@@ -1,0 +1,963 @@
+// Device kernels of the restarted Halpern PDHG solver (gfx950 / CDNA4).
+//
+// One solver step is two launches over fixed workgroup schedules:
+//   primal_step : y-gather SpMV over the rows of the explicit K^T, fused with
+//                 the primal PDHG step, box projection and Halpern blend;
+//   dual_step   : xbar-gather SpMV over the rows of K, fused with the dual
+//                 step, cone projection and Halpern blend; the last workgroup
+//                 of each LP (arrival counter) reduces that LP's block partial
+//                 sums in a fixed order and runs its restart / termination
+//                 controller on the device.
+// The path is bandwidth bound (about 2 flop per 12 bytes of matrix), so there
+// is no MFMA: the work is coalesced entry loads, gathers, LDS staging and
+// wave64 shuffle reductions.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "halp_types.h"
+#include "kernels.h"
+
+namespace halp {
+
+// ---------------------------------------------------------------------------
+// reductions (fixed order: results do not depend on scheduling)
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of kNS per-thread values over the block; result valid in s_out[0..kNS).
+__device__ __forceinline__ void block_sum_ns(double (&v)[kNS], double (*s_red)[kNS], double* s_out) {
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) v[s] = wave_sum(v[s]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) s_red[wave][s] = v[s];
+  }
+  __syncthreads();
+  if (threadIdx.x < kNS) {
+    double a = s_red[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) a += s_red[w][threadIdx.x];
+    s_out[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+template <class T>
+__device__ __forceinline__ T block_sum1(T v, double (*s_red)[kNS]) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) s_red[wave][0] = (double)v;
+  __syncthreads();
+  T a = (T)s_red[0][0];
+#pragma unroll
+  for (int w = 1; w < kThreads / 64; ++w) a += (T)s_red[w][0];
+  __syncthreads();
+  return a;
+}
+
+// Fixed-order sum of nb rows of kNS partials; all threads call, result in s_out.
+__device__ void sum_partials(const double* part, int nb, double (*s_red)[kNS], double* s_out) {
+  double v[kNS];
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) v[s] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) v[s] += part[(int64_t)b * kNS + s];
+  }
+  block_sum_ns(v, s_red, s_out);
+}
+
+__device__ __forceinline__ int group_size(int nrows) {
+  // largest power of two G <= 64 with nrows * G <= kThreads (at least 1)
+  int g = 64;
+  while (g > 1 && g * nrows > kThreads) g >>= 1;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// block SpMV: row sums of NV gathered vectors for the rows of one block.
+// Stream blocks (<= NB entries, <= kMaxRows rows): entries are loaded once,
+// coalesced, into registers; per gathered vector the products go to LDS and
+// groups of G lanes reduce each row.  Long blocks (one row): strided loop
+// with four accumulators and a block reduction.
+// Result: s_rsum[a][r - b.r0].
+// ---------------------------------------------------------------------------
+
+template <class T, int NV>
+__device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const T* __restrict__ val, const T* __restrict__ s0, const T* __restrict__ s1,
+                           const T* __restrict__ s2, T* s_prod, T (*s_rsum)[kMaxRows], int* s_rp,
+                           double (*s_red)[kNS], T scale0 = (T)1) {
+  constexpr int NB = Tile<T>::NB;
+  const int tid = threadIdx.x;
+  const int nrows = b.r1 - b.r0;
+  if (b.kind == BK_LONG) {
+    const int p0 = rp[b.r0], p1 = rp[b.r0 + 1];
+    T acc[NV][4];
+#pragma unroll
+    for (int a = 0; a < NV; ++a)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[a][u] = (T)0;
+    int e = p0 + tid;
+    for (; e + 3 * kThreads < p1; e += 4 * kThreads) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = ci[e + u * kThreads];
+        const T v = val[e + u * kThreads];
+        acc[0][u] += v * s0[c];
+        if constexpr (NV > 1) acc[1][u] += v * s1[c];
+        if constexpr (NV > 2) acc[2][u] += v * s2[c];
+      }
+    }
+    for (; e < p1; e += kThreads) {
+      const int c = ci[e];
+      const T v = val[e];
+      acc[0][0] += v * s0[c];
+      if constexpr (NV > 1) acc[1][0] += v * s1[c];
+      if constexpr (NV > 2) acc[2][0] += v * s2[c];
+    }
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+      T t = (acc[a][0] + acc[a][1]) + (acc[a][2] + acc[a][3]);
+      t = block_sum1(t, s_red);
+      if (tid == 0) s_rsum[a][0] = (a == 0) ? t * scale0 : t;
+    }
+    __syncthreads();
+    return;
+  }
+  for (int i = tid; i <= nrows; i += kThreads) s_rp[i] = rp[b.r0 + i];
+  __syncthreads();
+  const int p0 = s_rp[0];
+  const int nnz = s_rp[nrows] - p0;
+  constexpr int EPT = NB / kThreads;
+  int cidx[EPT];
+  T v[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < nnz) {
+      cidx[k] = ci[p0 + e];
+      v[k] = val[p0 + e];
+    }
+  }
+  const int G = group_size(nrows);
+  const int lane = tid & (G - 1);
+  const int rpb = kThreads / G;  // rows per pass
+#pragma unroll
+  for (int a = 0; a < NV; ++a) {
+    const T* __restrict__ src = (a == 0) ? s0 : (a == 1) ? s1 : s2;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = tid + k * kThreads;
+      if (e < nnz) s_prod[e] = v[k] * src[cidx[k]];
+    }
+    __syncthreads();
+    for (int base = 0; base < nrows; base += rpb) {
+      const int r = base + tid / G;
+      T acc = (T)0;
+      if (r < nrows) {
+        const int q1 = s_rp[r + 1] - p0;
+        for (int q = s_rp[r] - p0 + lane; q < q1; q += G) acc += s_prod[q];
+      }
+      for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0 && r < nrows) s_rsum[a][r] = (a == 0) ? acc * scale0 : acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step modes
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int step_mode(const InstState& S, int64_t g) {
+  if (S.status != ST_RUNNING) return M_SKIP;
+  if (S.phase == PH_EVAL) return M_EVAL;
+  if (S.phase == PH_RESID) return M_RESID;
+  const int64_t k = g - S.kbase;
+  if (k < 0) return M_SKIP;
+  if (k > 0 && (k % S.C) == 0) return M_CHECK;
+  return M_NORMAL;
+}
+
+template <class T>
+__device__ __forceinline__ T clampT(T v, T lo, T hi) {
+  return fmin(fmax(v, lo), hi);
+}
+
+// projection of a direction onto the recession cone of [l, u]
+template <class T>
+__device__ __forceinline__ T rec_proj(T d, bool lf, bool uf) {
+  return (lf && uf) ? (T)0 : lf ? fmax(d, (T)0) : uf ? fmin(d, (T)0) : d;
+}
+
+// ---------------------------------------------------------------------------
+// primal step (rows of K^T = variables)
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step) {
+  __shared__ T s_prod[Tile<T>::NB];
+  __shared__ T s_rsum[3][kMaxRows];
+  __shared__ int s_rp[kMaxRows + 1];
+  __shared__ double s_red[kThreads / 64][kNS];
+  __shared__ double s_out[kNS];
+
+  const Blk b = A.schedP[blockIdx.x];
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP) return;
+  if (mode == M_EVAL)
+    block_spmv<T, 3>(b, A.KT_rp, A.KT_ci, A.KT_v, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+  else if (mode != M_RESID)
+    block_spmv<T, 1>(b, A.KT_rp, A.KT_ci, A.KT_v, A.y, A.y, A.y, s_prod, s_rsum, s_rp, s_red);
+
+  double ps[kNS];
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
+  const int nrows = b.r1 - b.r0;
+  const int t = threadIdx.x;
+  if (t < nrows) {
+    const int64_t j = (int64_t)b.r0 + t;
+    const T cj = A.c[j], lj = A.l[j], uj = A.u[j];
+    const bool lf = isfinite(lj), uf = isfinite(uj);
+    if (mode == M_EVAL) {
+      const T g0 = s_rsum[0][t];
+      A.ktyp[j] = g0;
+      const double dc = A.Dc[j];
+      const double r = (double)cj - (double)g0;
+      const double lam = (lf && uf) ? r : lf ? fmax(r, 0.0) : uf ? fmin(r, 0.0) : 0.0;
+      const double rd = (r - lam) / dc;
+      ps[0] = rd * rd;
+      ps[1] = (lf ? (double)lj * fmax(lam, 0.0) : 0.0) - (uf ? (double)uj * fmax(-lam, 0.0) : 0.0);
+#pragma unroll
+      for (int a = 1; a <= 2; ++a) {
+        const double gg = (double)s_rsum[a][t];
+        double sv = 0.0, vv = 0.0;
+        if (gg > 0.0) {
+          if (uf) sv = (double)uj * gg; else vv = gg / dc;
+        } else if (gg < 0.0) {
+          if (lf) sv = (double)lj * gg; else vv = -gg / dc;
+        }
+        ps[2 * a] = sv;
+        ps[2 * a + 1] = vv * vv;
+      }
+    } else {
+      const bool resid = (mode == M_RESID);
+      const T xo = resid ? A.xT[j] : A.x[j];
+      const T kty = resid ? A.ktyp[j] : s_rsum[0][t];
+      const T tau = (T)S.tau;
+      const T xp = clampT<T>(xo - tau * (cj - kty), lj, uj);
+      const T xb = (T)2 * xp - xo;
+      const T x0j = resid ? xo : A.x0[j];
+      const int64_t k = g - S.kbase;
+      const double w = (double)(k + 1) / (double)(k + 2);
+      const T xh = S.reflect ? xb : xp;
+      const T xn = (T)w * xh + (T)(1.0 - w) * x0j;
+      A.xbar[j] = xb;
+      A.x[j] = xn;
+      if (resid) {
+        A.x0[j] = xo;
+        const double d = (double)xo - (double)xp;
+        ps[0] = d * d;
+      } else if (mode == M_CHECK) {
+        A.xT[j] = xp;
+        const double d = (double)xo - (double)xp;
+        const double ad = (double)xp - (double)x0j;
+        const T d1 = rec_proj<T>(xp - xo, lf, uf);
+        const T d2 = rec_proj<T>(xo - x0j, lf, uf);
+        A.cx1[j] = d1;
+        A.cx2[j] = d2;
+        ps[0] = d * d;
+        ps[1] = ad * ad;
+        ps[2] = (double)cj * (double)xp;
+        ps[3] = (double)cj * (double)d1;
+        ps[4] = (double)cj * (double)d2;
+      }
+    }
+  }
+  if (mode != M_NORMAL) {
+    block_sum_ns(ps, s_red, s_out);
+    if (t < kNS) A.partP[(int64_t)blockIdx.x * kNS + t] = s_out[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// controller: runs once per LP per check / eval / residual step
+// ---------------------------------------------------------------------------
+
+__device__ void controller(InstState& S, const double* sp, const double* sd, int mode, int64_t g,
+                           int* status_out, int inst) {
+  if (mode == M_CHECK) {
+    S.acc[A_DX2] = sp[0];
+    S.acc[A_AX2] = sp[1];
+    S.acc[A_POBJ] = sp[2];
+    S.acc[A_CD1] = sp[3];
+    S.acc[A_CD2] = sp[4];
+    S.acc[A_DY2] = sd[0];
+    S.acc[A_AY2] = sd[1];
+    S.acc[A_DOBJQ] = sd[2];
+    S.acc[A_QY1] = sd[3];
+    S.acc[A_QY2] = sd[4];
+    S.phase = PH_EVAL;
+    return;
+  }
+  if (mode == M_RESID) {
+    const double v = sp[0] / S.tau + sd[0] / S.sigma + 2.0 * sd[1];
+    S.r0 = sqrt(fmax(v, 0.0));
+    S.phase = PH_NORMAL;
+    return;
+  }
+  // eval step: the check candidate is T(z^{n,k}) from the previous step
+  const int64_t t = g - S.tbase;          // evaluations of T so far
+  const int64_t k = (g - 1) - S.kbase;    // inner counter of the check step
+  S.tbase += 1;
+  S.checks += 1;
+  const double res = sqrt(fmax(S.acc[A_DX2] / S.tau + S.acc[A_DY2] / S.sigma + 2.0 * sd[1], 0.0));
+  const double rel_p = sqrt(sd[0]) / (1.0 + S.qnorm);
+  const double rel_d = sqrt(sp[0]) / (1.0 + S.cnorm);
+  const double pobj = S.acc[A_POBJ];
+  const double dobj = S.acc[A_DOBJQ] + sp[1];
+  const double gap = fabs(pobj - dobj) / (1.0 + fabs(pobj) + fabs(dobj));
+  const double kkt = fmax(rel_p, fmax(rel_d, gap));
+  S.kkt = kkt;
+  S.rel_p = rel_p;
+  S.rel_d = rel_d;
+  S.rel_gap = gap;
+  S.pobj = pobj;
+  S.dobj = dobj;
+  S.resid = res;
+  S.iters = t;
+  int st = ST_RUNNING;
+  if (!isfinite(kkt) || !isfinite(res)) {
+    st = ST_NUMERICAL;
+  } else if (kkt <= S.tol) {
+    st = ST_OPTIMAL;
+  } else {
+    const double m1 = S.acc[A_QY1] - sp[2];
+    const double m2 = S.acc[A_QY2] - sp[4];
+    if (m1 > 0.0 && sqrt(sp[3]) <= S.eps_inf * m1) {
+      st = ST_PRIMAL_INFEAS;
+      S.ray = 1;
+    } else if (m2 > 0.0 && sqrt(sp[5]) <= S.eps_inf * m2) {
+      st = ST_PRIMAL_INFEAS;
+      S.ray = 2;
+    } else {
+      const double c1 = S.acc[A_CD1], c2 = S.acc[A_CD2];
+      if (c1 < 0.0 && sqrt(sd[2]) + sqrt(sd[3]) <= S.eps_inf * fabs(c1)) {
+        st = ST_DUAL_INFEAS;
+        S.ray = 1;
+      } else if (c2 < 0.0 && sqrt(sd[4]) + sqrt(sd[5]) <= S.eps_inf * fabs(c2)) {
+        st = ST_DUAL_INFEAS;
+        S.ray = 2;
+      }
+    }
+    if (st == ST_RUNNING && t >= S.max_iter) st = ST_ITER_LIMIT;
+  }
+  if (st != ST_RUNNING) {
+    S.status = st;
+    S.phase = PH_NORMAL;
+    status_out[inst] = st;
+    return;
+  }
+  const bool restart = (S.nrest == 0) || (res <= S.beta * S.r0) ||
+                       (S.artificial > 0.0 && (double)k >= S.artificial * (double)t);
+  if (restart) {
+    const double dX = sqrt(S.acc[A_AX2]), dY = sqrt(S.acc[A_AY2]);
+    if (S.primal_weight && dX > 1e-10 && dY > 1e-10)
+      S.omega = exp(0.5 * log(dY / dX) + 0.5 * log(S.omega));
+    S.tau = S.eta / S.omega;
+    S.sigma = S.eta * S.omega;
+    S.nrest += 1;
+    S.phase = PH_RESID;
+    S.kbase = g + 1;
+  } else {
+    S.phase = PH_NORMAL;
+    S.kbase += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dual step (rows of K = constraints) + per-LP controller
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
+  __shared__ T s_prod[Tile<T>::NB];
+  __shared__ T s_rsum[3][kMaxRows];
+  __shared__ int s_rp[kMaxRows + 1];
+  __shared__ double s_red[kThreads / 64][kNS];
+  __shared__ double s_out[kNS];
+  __shared__ double s_sum[2][kNS];
+  __shared__ int s_last;
+
+  const Blk b = A.schedD[blockIdx.x];
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP) return;
+  if (mode == M_EVAL)
+    block_spmv<T, 3>(b, A.K_rp, A.K_ci, A.K_v, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+  else
+    block_spmv<T, 1>(b, A.K_rp, A.K_ci, A.K_v, A.xbar, A.xbar, A.xbar, s_prod, s_rsum, s_rp, s_red);
+
+  double ps[kNS];
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
+  const int nrows = b.r1 - b.r0;
+  const int t = threadIdx.x;
+  if (t < nrows) {
+    const int64_t i = (int64_t)b.r0 + t;
+    const bool ineq = (i - S.row0) >= S.m_eq;
+    const T qi = A.q[i];
+    if (mode == M_EVAL) {
+      const T s0 = s_rsum[0][t];
+      A.kxp[i] = s0;
+      const double dr = A.Dr[i];
+      double r = ((double)s0 - (double)qi) / dr;
+      if (ineq) r = fmin(r, 0.0);
+      ps[0] = r * r;
+      ps[1] = (double)A.dy[i] * ((double)s0 - (double)A.kxbar[i]);
+#pragma unroll
+      for (int a = 1; a <= 2; ++a) {
+        const double av = (double)s_rsum[a][t] / dr;
+        if (ineq) {
+          const double mv = fmin(av, 0.0);
+          ps[2 * a + 1] = mv * mv;
+        } else {
+          ps[2 * a] = av * av;
+        }
+      }
+    } else {
+      const bool resid = (mode == M_RESID);
+      const T s0 = s_rsum[0][t];
+      const T yo = resid ? A.yT[i] : A.y[i];
+      const T sigma = (T)S.sigma;
+      T yp = yo + sigma * (qi - s0);
+      if (ineq) yp = fmax(yp, (T)0);
+      const T yb = (T)2 * yp - yo;
+      const T y0i = resid ? yo : A.y0[i];
+      const int64_t k = g - S.kbase;
+      const double w = (double)(k + 1) / (double)(k + 2);
+      const T yh = S.reflect ? yb : yp;
+      A.y[i] = (T)w * yh + (T)(1.0 - w) * y0i;
+      if (resid) {
+        A.y0[i] = yo;
+        const double d = (double)yo - (double)yp;
+        ps[0] = d * d;
+        ps[1] = d * (0.5 * ((double)A.kxp[i] - (double)s0));
+      } else if (mode == M_CHECK) {
+        A.yT[i] = yp;
+        const T dyv = yo - yp;
+        A.dy[i] = dyv;
+        A.kxbar[i] = s0;
+        T e1 = yp - yo, e2 = yo - y0i;
+        if (ineq) {
+          e1 = fmax(e1, (T)0);
+          e2 = fmax(e2, (T)0);
+        }
+        A.cy1[i] = e1;
+        A.cy2[i] = e2;
+        const double ad = (double)yp - (double)y0i;
+        ps[0] = (double)dyv * (double)dyv;
+        ps[1] = ad * ad;
+        ps[2] = (double)qi * (double)yp;
+        ps[3] = (double)qi * (double)e1;
+        ps[4] = (double)qi * (double)e2;
+      }
+    }
+  }
+  if (mode == M_NORMAL) return;
+
+  block_sum_ns(ps, s_red, s_out);
+  if (t < kNS) A.partD[(int64_t)blockIdx.x * kNS + t] = s_out[t];
+  __threadfence();
+  __syncthreads();
+  if (t == 0) {
+    const int nb = S.db1 - S.db0;
+    const int prev = __hip_atomic_fetch_add(&A.cnt[b.inst], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == nb - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  sum_partials(A.partP + (int64_t)S.pb0 * kNS, S.pb1 - S.pb0, s_red, s_sum[0]);
+  sum_partials(A.partD + (int64_t)S.db0 * kNS, S.db1 - S.db0, s_red, s_sum[1]);
+  if (t == 0) {
+    controller(A.st[b.inst], s_sum[0], s_sum[1], mode, g, A.status_out, b.inst);
+    A.cnt[b.inst] = 0;
+  }
+}
+
+__global__ void tick_kernel(int64_t* gbase, int64_t add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *gbase += add;
+}
+
+// ---------------------------------------------------------------------------
+// preprocessing: Ruiz / Pock-Chambolle factors and value scaling
+// ---------------------------------------------------------------------------
+
+// f[r] = sqrt(max_j |v_rj|) (op 0) or sqrt(sum_j |v_rj|) (op 1), 1 if zero;
+// D[r] /= f[r].
+__global__ __launch_bounds__(kThreads) void row_factor_kernel(const Blk* sched, const int32_t* rp,
+                                                              const double* val, int op, double expo,
+                                                              double* f, double* D) {
+  __shared__ double s_red[kThreads / 64][kNS];
+  const Blk b = sched[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int nrows = b.r1 - b.r0;
+  if (b.kind == BK_LONG) {
+    const int p0 = rp[b.r0], p1 = rp[b.r0 + 1];
+    double a = 0.0;
+    for (int e = p0 + tid; e < p1; e += kThreads) {
+      double v = fabs(val[e]);
+      if (op == 1 && expo != 1.0) v = pow(v, expo);
+      a = op == 0 ? fmax(a, v) : a + v;
+    }
+    // block reduce (max or sum) through LDS in fixed order
+    __syncthreads();
+    if (op == 0) {
+      for (int off = 32; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off, 64));
+    } else {
+      a = wave_sum(a);
+    }
+    if ((tid & 63) == 0) s_red[tid >> 6][0] = a;
+    __syncthreads();
+    if (tid == 0) {
+      double r = s_red[0][0];
+      for (int w = 1; w < kThreads / 64; ++w) r = op == 0 ? fmax(r, s_red[w][0]) : r + s_red[w][0];
+      double fr = sqrt(r);
+      if (!(fr > 0.0)) fr = 1.0;
+      f[b.r0] = fr;
+      D[b.r0] /= fr;
+    }
+    return;
+  }
+  const int G = group_size(nrows);
+  const int lane = tid & (G - 1);
+  for (int base = 0; base < nrows; base += kThreads / G) {
+    const int r = base + tid / G;
+    double a = 0.0;
+    if (r < nrows) {
+      const int p1 = rp[b.r0 + r + 1];
+      for (int e = rp[b.r0 + r] + lane; e < p1; e += G) {
+        double v = fabs(val[e]);
+        if (op == 1 && expo != 1.0) v = pow(v, expo);
+        a = op == 0 ? fmax(a, v) : a + v;
+      }
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) {
+      const double o = __shfl_xor(a, off, 64);
+      a = op == 0 ? fmax(a, o) : a + o;
+    }
+    if (lane == 0 && r < nrows) {
+      double fr = sqrt(a);
+      if (!(fr > 0.0)) fr = 1.0;
+      f[b.r0 + r] = fr;
+      D[b.r0 + r] /= fr;
+    }
+  }
+}
+
+// v_e <- v_e / fm[m-index] / fn[n-index]; for K the row is the m-index,
+// for K^T the row is the n-index.  Same operation order for both, so K~ and
+// (K~)^T hold bit-identical values.
+__global__ __launch_bounds__(kThreads) void scale_values_kernel(const Blk* sched, const int32_t* rp,
+                                                                const int32_t* ci, double* val,
+                                                                const double* fm, const double* fn,
+                                                                int transposed) {
+  const Blk b = sched[blockIdx.x];
+  const int nrows = b.r1 - b.r0;
+  const int tid = threadIdx.x;
+  const int G = (b.kind == BK_LONG) ? kThreads : group_size(nrows);
+  const int lane = tid & (G - 1);
+  for (int base = 0; base < nrows; base += kThreads / G) {
+    const int r = base + tid / G;
+    if (r >= nrows) continue;
+    const int row = b.r0 + r;
+    const int p1 = rp[row + 1];
+    for (int e = rp[row] + lane; e < p1; e += G) {
+      const int c = ci[e];
+      const double a = transposed ? fm[c] : fm[row];
+      const double d = transposed ? fn[row] : fn[c];
+      val[e] = val[e] / a / d;
+    }
+  }
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <class T>
+__global__ void cast_kernel(const double* src, T* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (T)src[i];
+}
+
+// per-LP unscaled norms ||q|| and ||c|| (one block per LP, fixed order)
+// per-LP norms: ||q||, ||c|| (unscaled) and ||D_r q||, ||D_c c|| (scaled),
+// one block per LP, fixed order; the scaled pair goes to out[2 * block + {0,1}]
+__global__ __launch_bounds__(kThreads) void inst_norms_kernel(InstState* st, const int* ids,
+                                                              const double* q, const double* c,
+                                                              const double* Dr, const double* Dc,
+                                                              double* out) {
+  __shared__ double s_red[kThreads / 64][kNS];
+  __shared__ double s_out[kNS];
+  InstState& S = st[ids[blockIdx.x]];
+  double v[kNS];
+  for (int s = 0; s < kNS; ++s) v[s] = 0.0;
+  for (int64_t i = threadIdx.x; i < S.m; i += kThreads) {
+    const double a = q[S.row0 + i];
+    const double b = Dr[S.row0 + i] * a;
+    v[0] += a * a;
+    v[2] += b * b;
+  }
+  for (int64_t j = threadIdx.x; j < S.n; j += kThreads) {
+    const double a = c[S.col0 + j];
+    const double b = Dc[S.col0 + j] * a;
+    v[1] += a * a;
+    v[3] += b * b;
+  }
+  block_sum_ns(v, s_red, s_out);
+  if (threadIdx.x == 0) {
+    S.qnorm = sqrt(s_out[0]);
+    S.cnorm = sqrt(s_out[1]);
+    out[2 * blockIdx.x] = sqrt(s_out[2]);
+    out[2 * blockIdx.x + 1] = sqrt(s_out[3]);
+  }
+}
+
+// scaled vectors over the rows of the given schedules
+template <class T>
+__global__ __launch_bounds__(kThreads) void scale_primal_kernel(const Blk* schedP, const double* Dc,
+                                                                const double* c, const double* l,
+                                                                const double* u, T* cs, T* ls, T* us) {
+  const Blk b = schedP[blockIdx.x];
+  if ((int)threadIdx.x < b.r1 - b.r0) {
+    const int64_t j = (int64_t)b.r0 + threadIdx.x;
+    cs[j] = (T)(Dc[j] * c[j]);
+    ls[j] = (T)(l[j] / Dc[j]);
+    us[j] = (T)(u[j] / Dc[j]);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void scale_dual_kernel(const Blk* schedD, const double* Dr,
+                                                              const double* q, T* qs) {
+  const Blk b = schedD[blockIdx.x];
+  if ((int)threadIdx.x < b.r1 - b.r0) {
+    const int64_t i = (int64_t)b.r0 + threadIdx.x;
+    qs[i] = (T)(Dr[i] * q[i]);
+  }
+}
+
+// write the host-prepared states of new LPs and clear their status words
+__global__ void write_states_kernel(InstState* st, int* status_out, int* cnt, const int* ids,
+                                    const InstState* src, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    st[ids[i]] = src[i];
+    status_out[ids[i]] = src[i].status;
+    cnt[ids[i]] = 0;
+  }
+}
+
+// schedule ranges of live LPs after a schedule rebuild
+__global__ void set_ranges_kernel(InstState* st, const int* ids, const int4* ranges, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    InstState& S = st[ids[i]];
+    const int4 r = ranges[i];
+    S.pb0 = r.x;
+    S.pb1 = r.y;
+    S.db0 = r.z;
+    S.db1 = r.w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// power iteration on K~^T K~ (per LP)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+  uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// w = SplitMix64 uniform [-1, 1) start vector over each LP's variables, and
+// the block partial of sum w^2
+__global__ __launch_bounds__(kThreads) void pw_start_kernel(const Blk* schedP, const InstState* st,
+                                                            uint64_t seed, double* w, double* partP) {
+  __shared__ double s_red[kThreads / 64][kNS];
+  __shared__ double s_out[kNS];
+  const Blk b = schedP[blockIdx.x];
+  const InstState& S = st[b.inst];
+  double v[kNS];
+  for (int s = 0; s < kNS; ++s) v[s] = 0.0;
+  const int nrows = b.r1 - b.r0;
+  if ((int)threadIdx.x < nrows) {
+    const int64_t j = (int64_t)b.r0 + threadIdx.x;
+    const uint64_t z = splitmix64_at(seed, (uint64_t)(j - S.col0));
+    const double u = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    w[j] = u;
+    v[0] = u * u;
+  }
+  block_sum_ns(v, s_red, s_out);
+  if (threadIdx.x < kNS) partP[(int64_t)blockIdx.x * kNS + threadIdx.x] = s_out[threadIdx.x];
+}
+
+// u = pw_scale * K~ w over the rows of K (dual schedule)
+__global__ __launch_bounds__(kThreads) void pw_forward_kernel(const Blk* schedD, const InstState* st,
+                                                              const int32_t* rp, const int32_t* ci,
+                                                              const double* val, const double* w,
+                                                              double* u) {
+  __shared__ double s_prod[Tile<double>::NB];
+  __shared__ double s_rsum[3][kMaxRows];
+  __shared__ int s_rp[kMaxRows + 1];
+  __shared__ double s_red[kThreads / 64][kNS];
+  const Blk b = schedD[blockIdx.x];
+  const InstState& S = st[b.inst];
+  if (S.pw_done) return;
+  block_spmv<double, 1>(b, rp, ci, val, w, w, w, s_prod, s_rsum, s_rp, s_red, S.pw_scale);
+  const int nrows = b.r1 - b.r0;
+  if ((int)threadIdx.x < nrows) u[(int64_t)b.r0 + threadIdx.x] = s_rsum[0][threadIdx.x];
+}
+
+// w = K~^T u over the rows of K^T (primal schedule), with the partial sum w^2
+__global__ __launch_bounds__(kThreads) void pw_backward_kernel(const Blk* schedP, const InstState* st,
+                                                               const int32_t* rp, const int32_t* ci,
+                                                               const double* val, const double* u,
+                                                               double* w, double* partP) {
+  __shared__ double s_prod[Tile<double>::NB];
+  __shared__ double s_rsum[3][kMaxRows];
+  __shared__ int s_rp[kMaxRows + 1];
+  __shared__ double s_red[kThreads / 64][kNS];
+  __shared__ double s_out[kNS];
+  const Blk b = schedP[blockIdx.x];
+  const InstState& S = st[b.inst];
+  if (S.pw_done) return;
+  block_spmv<double, 1>(b, rp, ci, val, u, u, u, s_prod, s_rsum, s_rp, s_red);
+  double v[kNS];
+  for (int s = 0; s < kNS; ++s) v[s] = 0.0;
+  const int nrows = b.r1 - b.r0;
+  if ((int)threadIdx.x < nrows) {
+    const double a = s_rsum[0][threadIdx.x];
+    w[(int64_t)b.r0 + threadIdx.x] = a;
+    v[0] = a * a;
+  }
+  block_sum_ns(v, s_red, s_out);
+  if (threadIdx.x < kNS) partP[(int64_t)blockIdx.x * kNS + threadIdx.x] = s_out[threadIdx.x];
+}
+
+// one block per LP: ||w|| from the partials, estimate sqrt(||w||), stop rule
+__global__ __launch_bounds__(kThreads) void pw_control_kernel(InstState* st, const int* ids,
+                                                              const int4* ranges, const double* partP,
+                                                              int start, int min_iters, int max_iters,
+                                                              double rtol, int* active) {
+  __shared__ double s_red[kThreads / 64][kNS];
+  __shared__ double s_sum[kNS];
+  InstState& S = st[ids[blockIdx.x]];
+  if (S.pw_done) return;
+  const int4 rg = ranges[blockIdx.x];
+  sum_partials(partP + (int64_t)rg.x * kNS, rg.y - rg.x, s_red, s_sum);
+  if (threadIdx.x != 0) return;
+  const double nw = sqrt(s_sum[0]);
+  if (start) {
+    S.pw_scale = nw > 0.0 ? 1.0 / nw : 0.0;
+    S.pw_iter = 0;
+    S.pw_prev = -1.0;
+    S.sigma_hat = 0.0;
+    if (!(nw > 0.0)) S.pw_done = 1;
+    else atomicAdd(active, 1);
+    return;
+  }
+  S.pw_iter += 1;
+  if (!(nw > 0.0)) {
+    S.sigma_hat = 0.0;
+    S.pw_done = 1;
+    return;
+  }
+  const double s = sqrt(nw);
+  S.sigma_hat = s;
+  S.pw_scale = 1.0 / nw;
+  if ((S.pw_prev >= 0.0 && S.pw_iter >= min_iters && fabs(s - S.pw_prev) <= rtol * s) ||
+      S.pw_iter >= max_iters) {
+    S.pw_done = 1;
+    return;
+  }
+  S.pw_prev = s;
+  atomicAdd(active, 1);
+}
+
+// ---------------------------------------------------------------------------
+// CSR transpose helpers, iterate initialisation, results, validation
+// ---------------------------------------------------------------------------
+
+__global__ void shift_copy_kernel(int32_t* dst, const int32_t* src, int64_t n, int64_t add) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (int32_t)(src[i] + add);
+}
+
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+// rowid[e - z0] = row, for every entry of the rows in the dual schedule
+__global__ __launch_bounds__(kThreads) void row_ids_kernel(const Blk* sched, const int32_t* rp,
+                                                           int64_t z0, int32_t* rowid) {
+  const Blk b = sched[blockIdx.x];
+  const int nrows = b.r1 - b.r0;
+  const int G = (b.kind == BK_LONG) ? kThreads : group_size(nrows);
+  const int lane = threadIdx.x & (G - 1);
+  for (int base = 0; base < nrows; base += kThreads / G) {
+    const int r = base + threadIdx.x / G;
+    if (r >= nrows) continue;
+    const int row = b.r0 + r;
+    const int p1 = rp[row + 1];
+    for (int e = rp[row] + lane; e < p1; e += G) rowid[e - z0] = row;
+  }
+}
+
+template <class V>
+__global__ void transpose_gather_kernel(const int32_t* perm, const int32_t* rowid, const V* val,
+                                        int64_t z0, int64_t nnz, int32_t* kt_ci, V* kt_val) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t e = perm[p];
+  kt_ci[z0 + p] = rowid[e];
+  kt_val[z0 + p] = val[z0 + e];
+}
+
+// kt_rp[j] = z0 + #{sorted keys < j} for space positions j in [c0, c1]
+__global__ void transpose_rowptr_kernel(const int32_t* keys, int64_t nnz, int64_t z0, int64_t c0,
+                                        int64_t c1, int32_t* kt_rp) {
+  const int64_t j = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > c1) return;
+  int64_t lo = 0, hi = nnz;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < j) lo = mid + 1; else hi = mid;
+  }
+  kt_rp[j] = (int32_t)(z0 + lo);
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void init_primal_kernel(const Blk* schedP, const T* l, const T* u,
+                                                               T* x, T* x0) {
+  const Blk b = schedP[blockIdx.x];
+  const int nrows = b.r1 - b.r0;
+  if ((int)threadIdx.x < nrows) {
+    const int64_t j = (int64_t)b.r0 + threadIdx.x;
+    const T v = clampT<T>((T)0, l[j], u[j]);
+    x[j] = v;
+    x0[j] = v;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void init_dual_kernel(const Blk* schedD, T* y, T* y0) {
+  const Blk b = schedD[blockIdx.x];
+  const int nrows = b.r1 - b.r0;
+  if ((int)threadIdx.x < nrows) {
+    const int64_t i = (int64_t)b.r0 + threadIdx.x;
+    y[i] = (T)0;
+    y0[i] = (T)0;
+  }
+}
+
+template <class T>
+__global__ void unscale_kernel(const T* v, const double* D, int64_t off, int64_t n, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = D[off + i] * (double)v[off + i];
+}
+
+template <class T>
+__global__ void copy_state_kernel(const T* src, double* dst, int64_t off, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)src[off + i];
+}
+
+// flags: 1 bad row pointers, 2 column out of range or not increasing, 4 non-finite value
+__global__ void validate_csr_kernel(const int32_t* rp, const int32_t* ci, const double* val, int64_t m,
+                                    int64_t n, int64_t nnz, int* flags) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0 && (rp[0] != 0 || rp[m] != nnz)) atomicOr(flags, 1);
+  if (r >= m) return;
+  const int64_t p0 = rp[r], p1 = rp[r + 1];
+  if (p1 < p0 || p0 < 0 || p1 > nnz) {
+    atomicOr(flags, 1);
+    return;
+  }
+  int64_t prev = -1;
+  for (int64_t e = p0; e < p1; ++e) {
+    const int64_t c = ci[e];
+    if (c < 0 || c >= n || c <= prev) atomicOr(flags, 2);
+    prev = c;
+    if (!isfinite(val[e])) atomicOr(flags, 4);
+  }
+}
+
+// flags: 8 non-finite c or rhs, 16 bad bounds
+__global__ void validate_vectors_kernel(const double* c, const double* rhs, const double* lb,
+                                        const double* ub, int64_t m, int64_t n, int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && !isfinite(rhs[i])) atomicOr(flags, 8);
+  if (i < n) {
+    if (!isfinite(c[i])) atomicOr(flags, 8);
+    const double a = lb[i], b = ub[i];
+    if (isnan(a) || isnan(b) || a > b || a == INFINITY || b == -INFINITY) atomicOr(flags, 16);
+  }
+}
+
+__global__ void set_limit_status_kernel(InstState* st, int* status_out, int ninst, int code) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ninst && st[i].status == ST_RUNNING) {
+    st[i].status = code;
+    status_out[i] = code;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations
+// ---------------------------------------------------------------------------
+
+template __global__ void primal_step<double>(IterArgs<double>, int);
+template __global__ void primal_step<float>(IterArgs<float>, int);
+template __global__ void dual_step<double>(IterArgs<double>, int);
+template __global__ void dual_step<float>(IterArgs<float>, int);
+template __global__ void cast_kernel<float>(const double*, float*, int64_t);
+template __global__ void scale_primal_kernel<double>(const Blk*, const double*, const double*,
+                                                     const double*, const double*, double*, double*,
+                                                     double*);
+template __global__ void scale_primal_kernel<float>(const Blk*, const double*, const double*,
+                                                    const double*, const double*, float*, float*, float*);
+template __global__ void scale_dual_kernel<double>(const Blk*, const double*, const double*, double*);
+template __global__ void scale_dual_kernel<float>(const Blk*, const double*, const double*, float*);
+template __global__ void transpose_gather_kernel<double>(const int32_t*, const int32_t*, const double*,
+                                                         int64_t, int64_t, int32_t*, double*);
+template __global__ void init_primal_kernel<double>(const Blk*, const double*, const double*, double*,
+                                                    double*);
+template __global__ void init_primal_kernel<float>(const Blk*, const float*, const float*, float*, float*);
+template __global__ void init_dual_kernel<double>(const Blk*, double*, double*);
+template __global__ void init_dual_kernel<float>(const Blk*, float*, float*);
+template __global__ void unscale_kernel<double>(const double*, const double*, int64_t, int64_t, double*);
+template __global__ void unscale_kernel<float>(const float*, const double*, int64_t, int64_t, double*);
+template __global__ void copy_state_kernel<double>(const double*, double*, int64_t, int64_t);
+template __global__ void copy_state_kernel<float>(const float*, double*, int64_t, int64_t);
+
+}  // namespace halp

@@ -1,0 +1,260 @@
+"""GPU parity tests: the HIP solver (through the C ABI) against the CPU oracle.
+
+Tolerances: FP64 trajectories agree to 1e-10 relative after ~1000 iterations
+(both sides run the same algorithm; they differ only in rounding order:
+tree-ordered reductions and fused multiply-adds on the GPU).  Final answers
+are compared through quantities that are unique -- status, objective,
+relative KKT error recomputed by the oracle -- never x or y of a possibly
+non-unique optimum.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+
+halp = pytest.importorskip("paper_2407_16144_amd")
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+METHODS = [("rhpdhg", halp.LP_METHOD_RHPDHG), ("r2hpdhg", halp.LP_METHOD_R2HPDHG)]
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+
+
+def _gpu(lp, tol, max_iter, **kw):
+    opt = halp.lp_default_options(**kw)
+    return halp.solve_lp(lp, tol=tol, max_iter=max_iter, opt=opt)
+
+
+@pytest.mark.parametrize("name,code", METHODS)
+def test_tiny_final_solution_matches_oracle(name, code):
+    lp = lpgen.tiny()
+    print(f"case tiny {name}", flush=True)
+    res, x, y, _ = _gpu(lp, 1e-8, 500_000, method=code)
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=1e-8))
+    assert res["status"] == halp.LP_OPTIMAL and ref.status == core.OPTIMAL
+    kkt, parts = oracle.rel_kkt(lp, x, y)
+    assert kkt <= 1e-8 * (1 + 1e-6), parts
+    assert abs(res["rel_kkt"] - kkt) <= 1e-10
+    assert abs(res["pobj"] - ref.pobj) <= 1e-7 * (1 + abs(ref.pobj))
+    # same algorithm, same decisions: identical iteration and restart counts
+    assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
+    assert res["sigma_hat"] == pytest.approx(ref.sigma_hat, rel=1e-12)
+    assert res["power_iters"] == ref.power_iters
+
+
+@pytest.mark.parametrize("name,code", METHODS)
+@pytest.mark.parametrize("seed", [lpgen.BASE_SEED, 17])
+def test_trajectory_parity_1000_iterations(name, code, seed):
+    """Iterates after ~1000 evaluations of T (the first check at or past
+    1000) agree with the oracle to 1e-10 relative."""
+    lp = lpgen.tiny(seed)
+    print(f"case trajectory {name} seed={seed}", flush=True)
+    res, x, y, _ = _gpu(lp, 0.0, 1000, method=code)
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=0.0, max_iter=1000))
+    margins = [e["margin"] for e in ref.log if e["n"] > 0]
+    assert min(margins, default=1.0) > 1e-8, "restart decision too close to call"
+    assert res["status"] == halp.LP_ITER_LIMIT == ref.status
+    assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
+    assert _rel(x, ref.x) <= 1e-10
+    assert _rel(y, ref.y) <= 1e-10
+
+
+def test_fixed_step_trajectory_parity_powerlaw():
+    """A power-law instance with rows long enough for several workgroups,
+    empty-ish columns and free variables, run with the oracle's step size."""
+    lp = lpgen.scaled_powerlaw(5, 700, 2400)
+    print("case powerlaw fixed eta", flush=True)
+    P = core.scaled_problem(lp)
+    s, _ = oracle.power_iteration(P.K, 0)
+    eta = 0.9 / s
+    res, x, y, _ = _gpu(lp, 0.0, 640, eta=eta)
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=640, eta=eta))
+    assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
+    assert _rel(x, ref.x) <= 1e-10
+    assert _rel(y, ref.y) <= 1e-10
+
+
+@pytest.mark.parametrize("seed", [lpgen.BASE_SEED, 1, 2, 3])
+def test_tiny_copy_brute_force(seed):
+    lp = lpgen.tiny_copy(seed)
+    best, _ = oracle.vertex_enumeration(lp)
+    if best is None:
+        pytest.skip("infeasible draw")
+    print(f"case tiny_copy seed={seed}", flush=True)
+    for _, code in METHODS:
+        res, x, y, _ = _gpu(lp, 1e-9, 500_000, method=code)
+        assert res["status"] == halp.LP_OPTIMAL
+        assert abs(res["pobj"] - best) <= 1e-7 * (1 + abs(best))
+
+
+@pytest.mark.parametrize("name,code", METHODS)
+def test_primal_infeasible_certificate(name, code):
+    lp = lpgen.add_contradictory_rows(lpgen.tiny(5), seed=1)
+    print(f"case primal infeasible {name}", flush=True)
+    res, x, y, ray = _gpu(lp, 1e-8, 200_000, method=code)
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=1e-8, max_iter=200_000))
+    assert res["status"] == halp.LP_PRIMAL_INFEASIBLE == ref.status
+    assert oracle.primal_ray_check(lp, ray)[0]
+    assert res["iters"] == ref.iters
+    assert _rel(ray, ref.ray) <= 1e-8
+
+
+@pytest.mark.parametrize("name,code", METHODS)
+def test_dual_infeasible_certificate(name, code):
+    lp = lpgen.add_unbounded_column(lpgen.scaled_powerlaw(6, 40, 120), seed=2)
+    print(f"case dual infeasible {name}", flush=True)
+    res, x, y, ray = _gpu(lp, 1e-8, 200_000, method=code)
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=1e-8, max_iter=200_000))
+    assert res["status"] == halp.LP_DUAL_INFEASIBLE == ref.status
+    assert oracle.dual_ray_check(lp, ray)[0]
+
+
+def test_no_constraints():
+    """m = 0: the minimum of c^T x over the box, at a vertex of the box."""
+    n = 50
+    rng = np.random.default_rng(0)
+    c = rng.standard_normal(n)
+    lp = lpgen.LP(n, 0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), c,
+                  np.zeros(0), -np.ones(n), 2 * np.ones(n))
+    print("case m=0", flush=True)
+    res, x, y, _ = _gpu(lp, 1e-10, 100_000)
+    assert res["status"] == halp.LP_OPTIMAL
+    assert np.allclose(x, np.where(c > 0, -1.0, 2.0), atol=1e-9)
+
+
+def test_empty_rows_and_columns():
+    """An empty equality row with zero rhs and an empty column are legal."""
+    lp = lpgen.tiny(3)
+    m = lp.m
+    rp = np.concatenate([lp.rowptr[:1], lp.rowptr])        # new empty row 0
+    lp2 = lpgen.LP(lp.n + 1, lp.m_eq + 1, lp.m_ineq, rp.astype(np.int32), lp.col, lp.val,
+                   np.concatenate([lp.c, [1.0]]), np.concatenate([[0.0], lp.rhs]),
+                   np.concatenate([lp.lb, [0.0]]), np.concatenate([lp.ub, [3.0]]))
+    print("case empty row/col", flush=True)
+    res, x, y, _ = _gpu(lp2, 1e-8, 500_000)
+    ref = oracle.solve(lp2, oracle.Options(tol=1e-8))
+    assert res["status"] == halp.LP_OPTIMAL == ref.status
+    assert res["iters"] == ref.iters
+    assert x[-1] == pytest.approx(0.0, abs=1e-8)
+    assert abs(res["pobj"] - ref.pobj) <= 1e-7 * (1 + abs(ref.pobj))
+
+
+def test_rows_longer_than_a_workgroup_tile():
+    """Rows with more entries than one stream tile (2048) take the long-row
+    path; compare the trajectory with the oracle."""
+    base = lpgen.scaled_powerlaw(8, 300, 6000)
+    rng = np.random.default_rng(4)
+    dense_cols = np.sort(rng.choice(base.n, 4500, replace=False)).astype(np.int32)
+    vals = rng.standard_normal(4500)
+    xs = base.meta["x_plant"]
+    rp = base.rowptr.astype(np.int64)
+    me = base.m_eq
+    col = np.concatenate([base.col[:rp[me]], dense_cols, base.col[rp[me]:]])
+    val = np.concatenate([base.val[:rp[me]], vals, base.val[rp[me]:]])
+    rowptr = np.concatenate([rp[:me + 1], rp[me:] + 4500]).astype(np.int32)
+    rhs = np.concatenate([base.rhs[:me], [vals @ xs[dense_cols]], base.rhs[me:]])
+    lp = lpgen.LP(base.n, me + 1, base.m_ineq, rowptr, col, val, base.c, rhs, base.lb, base.ub)
+    print("case long row", flush=True)
+    P = core.scaled_problem(lp)
+    s, _ = oracle.power_iteration(P.K, 0)
+    res, x, y, _ = _gpu(lp, 0.0, 320, eta=0.9 / s)
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=320, eta=0.9 / s))
+    assert res["iters"] == ref.iters
+    assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
+
+
+def test_unsorted_duplicate_columns_are_canonicalised():
+    lp = lpgen.tiny(6)
+    m = lp.m
+    # reverse each row and split every first entry into two halves
+    rows_c, rows_v, rp = [], [], [0]
+    for i in range(m):
+        cs = list(lp.col[lp.rowptr[i]:lp.rowptr[i + 1]][::-1])
+        vs = list(lp.val[lp.rowptr[i]:lp.rowptr[i + 1]][::-1])
+        cs.append(cs[0])
+        vs[0] *= 0.5
+        vs.append(vs[0])
+        rows_c += cs
+        rows_v += vs
+        rp.append(len(rows_c))
+    lp2 = lpgen.LP(lp.n, lp.m_eq, lp.m_ineq, np.array(rp, np.int32), np.array(rows_c, np.int32),
+                   np.array(rows_v), lp.c, lp.rhs, lp.lb, lp.ub)
+    print("case canonicalise", flush=True)
+    r1, x1, y1, _ = _gpu(lp, 1e-7, 200_000)
+    r2, x2, y2, _ = _gpu(lp2, 1e-7, 200_000)
+    assert r1["iters"] == r2["iters"]
+    assert _rel(x1, x2) <= 1e-12 and _rel(y1, y2) <= 1e-12
+
+
+def test_device_inputs_equal_host_inputs():
+    lp = lpgen.tiny(7)
+    print("case device inputs", flush=True)
+    opt = halp.lp_default_options()
+    r1, x1, y1, _ = halp.solve_lp(lp, tol=1e-8, max_iter=200_000, opt=opt)
+    r2, x2, y2, _ = halp.solve_lp(lp, tol=1e-8, max_iter=200_000, opt=opt, on_device=True)
+    assert r1["iters"] == r2["iters"]
+    assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
+
+
+def test_batch_results_equal_single_results():
+    """Each LP of a ragged batch gives bit-identical results to solving it alone."""
+    lps = [lpgen.scaled_powerlaw(100 + i, m, 3 * m) for i, m in enumerate([40, 300, 75, 1200, 10])]
+    lps.append(lpgen.add_contradictory_rows(lpgen.tiny(8), seed=2))
+    print("case batch", flush=True)
+    h = halp.lp_batch_create(lps)
+    try:
+        halp.lp_batch_solve(h, 1e-6, 100_000)
+        for i, lp in enumerate(lps):
+            rb = halp.lp_batch_status(h, i).as_dict()
+            xb, yb = halp.lp_batch_get_solution(h, i, lp.n, lp.m)
+            rs, xs, ys, _ = _gpu(lp, 1e-6, 100_000)
+            assert rb["status"] == rs["status"] and rb["iters"] == rs["iters"], (i, rb, rs)
+            assert np.array_equal(xb, xs) and np.array_equal(yb, ys), i
+    finally:
+        halp.lp_batch_destroy(h)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_graph_and_stream_launch_agree(graph):
+    lp = lpgen.tiny(9)
+    print(f"case graph={graph}", flush=True)
+    r, x, y, _ = _gpu(lp, 1e-8, 200_000, use_graph=graph)
+    r2, x2, y2, _ = _gpu(lp, 1e-8, 200_000, use_graph=1 - graph, chunk=16)
+    assert r["iters"] == r2["iters"]
+    assert np.array_equal(x, x2) and np.array_equal(y, y2)
+
+
+def test_fp32_mode_reaches_moderate_accuracy():
+    lp = lpgen.tiny()
+    print("case fp32", flush=True)
+    res, x, y, _ = _gpu(lp, 1e-4, 200_000, precision=halp.LP_PREC_FP32)
+    assert res["status"] == halp.LP_OPTIMAL
+    kkt, parts = oracle.rel_kkt(lp, x, y)
+    assert kkt <= 2e-4, parts
+
+
+def test_iteration_limit_and_errors():
+    lp = lpgen.tiny()
+    print("case limits", flush=True)
+    res, *_ = _gpu(lp, 1e-12, 1)
+    assert res["status"] == halp.LP_ITER_LIMIT and res["iters"] == 65
+    h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, lp.c, lp.rhs, lp.lb, lp.ub)
+    try:
+        with pytest.raises(halp.HalpError) as ei:
+            halp.lp_get_solution(h, lp.n, lp.m)
+        assert ei.value.code == halp.LP_ERR_STATE
+        halp.lp_solve(h, 1e-4, 100_000)
+        with pytest.raises(halp.HalpError):
+            halp.lp_get_certificate(h, lp.m)      # optimal: no certificate
+        with pytest.raises(halp.HalpError):
+            halp.lp_solve(h, 1e-4, 100_000)       # one solve per handle
+    finally:
+        halp.lp_destroy(h)
