@@ -72,9 +72,12 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
+    ap.add_argument("--time-limit", type=float, default=600.0)
     ap.add_argument("--workload", default="large", choices=["large", "tiny"])
     ap.add_argument("--profile-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=float, default=0.0,
+                    help="also run a plain device copy of this many MB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})",
@@ -87,6 +90,14 @@ def main():
     import paper_2407_16144_amd as halp
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mb > 0:
+        nel = int(args.copy_probe_mb * 1e6 / 8)
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy probe: {nel * 8} bytes read and written per launch", file=sys.stderr, flush=True)
     lp = lpgen.large_single() if args.workload == "large" else lpgen.tiny()
     dev = torch.device("cuda", 0)
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
@@ -103,7 +114,7 @@ def main():
         h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,
                            stream=stream.cuda_stream, opt=opt)
         try:
-            halp.lp_solve(h, args.tol, args.max_iter)
+            halp.lp_solve(h, args.tol, args.max_iter, args.time_limit)
             r = halp.lp_status(h).as_dict()
             kt = halp.lp_kernel_times(h)
         finally:

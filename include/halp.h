@@ -94,6 +94,9 @@ typedef struct {
   int use_graph;            /* 1: replay chunks as a captured hipGraph */
   int profile;              /* k > 0: time every k-th chunk's two kernels with HIP
                                events on the solver's stream (see lp_kernel_times) */
+  int64_t slice_min_bytes;  /* store K (K^T) column-sliced, one slice per XCD, when
+                               the vector its product gathers exceeds this many
+                               bytes (default 2 MiB; < 0 never) */
   int verbose;
 } lp_options;
 

@@ -42,7 +42,7 @@ class lp_options(C.Structure):
                 ("power_rtol", C.c_double), ("eps_infeas", C.c_double),
                 ("primal_weight", C.c_int), ("seed", C.c_uint64), ("eta", C.c_double),
                 ("omega0", C.c_double), ("chunk", C.c_int), ("use_graph", C.c_int),
-                ("profile", C.c_int), ("verbose", C.c_int)]
+                ("profile", C.c_int), ("slice_min_bytes", C.c_int64), ("verbose", C.c_int)]
 
 
 class lp_result(C.Structure):

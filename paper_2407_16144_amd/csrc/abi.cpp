@@ -58,6 +58,7 @@ halp::Options to_opts(const lp_options* o) {
   r.chunk = o->chunk;
   r.use_graph = o->use_graph;
   r.profile = o->profile;
+  r.slice_min_bytes = o->slice_min_bytes;
   r.verbose = o->verbose;
   return r;
 }
@@ -190,6 +191,7 @@ void lp_default_options(lp_options* o) {
   o->chunk = d.chunk;
   o->use_graph = d.use_graph;
   o->profile = d.profile;
+  o->slice_min_bytes = d.slice_min_bytes;
   o->verbose = d.verbose;
 }
 

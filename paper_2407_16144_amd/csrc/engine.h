@@ -46,6 +46,7 @@ struct Options {
   int chunk = 64;
   int use_graph = 1;
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
+  int64_t slice_min_bytes = 2 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
   int verbose = 0;
 };
 

@@ -88,39 +88,121 @@ static void dfree(P*& p) {
 // Workgroup schedule of one LP's rows: consecutive rows are packed into
 // "stream" blocks of at most NB entries and kMaxRows rows; a row with more
 // than NB entries gets a "long" block.  Every LP gets at least one block so
-// that its controller always runs.
+// that its controller always runs.  gid counts blocks from 0 (offset when the
+// schedules of all LPs are concatenated).
 static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int inst, int NB,
                          std::vector<Blk>& out) {
   const size_t first = out.size();
   int64_t start = 0, acc = 0;
-  auto flush = [&](int64_t a, int64_t b) {
-    if (b > a) out.push_back(Blk{(int32_t)(base + a), (int32_t)(base + b), inst, BK_STREAM});
+  auto emit = [&](int64_t a, int64_t b, int kind) {
+    Blk k;
+    k.r0 = (int32_t)(base + a);
+    k.r1 = (int32_t)(base + b);
+    k.inst = inst;
+    k.meta = blk_meta(kind, 1, 0);
+    k.gid = (int32_t)(out.size() - first);
+    k.rp_off = 0;
+    k.p0 = rp[a];
+    k.pn = rp[b] - rp[a];
+    out.push_back(k);
   };
   for (int64_t r = 0; r < nrows; ++r) {
     const int64_t len = (int64_t)rp[r + 1] - rp[r];
     if (len > NB) {
-      flush(start, r);
-      out.push_back(Blk{(int32_t)(base + r), (int32_t)(base + r + 1), inst, BK_LONG});
+      if (r > start) emit(start, r, BK_STREAM);
+      emit(r, r + 1, BK_LONG);
       start = r + 1;
       acc = 0;
       continue;
     }
     if (acc + len > NB || (r - start) >= kMaxRows) {
-      flush(start, r);
+      if (r > start) emit(start, r, BK_STREAM);
       start = r;
       acc = 0;
     }
     acc += len;
   }
-  flush(start, nrows);
-  if (out.size() == first) out.push_back(Blk{(int32_t)base, (int32_t)base, inst, BK_STREAM});
+  if (nrows > start) emit(start, nrows, BK_STREAM);
+  if (out.size() == first) emit(0, 0, BK_STREAM);
+}
+
+// Column-sliced schedule of one LP's rows.  cnt[r * kSlices + s] counts row
+// r's entries in column slice s.  Rows are grouped so that every slice of a
+// group holds at most NB entries (a row with more gets a group of its own and
+// "long" slice blocks).  For every group: one epilogue block (nsl = kSlices)
+// in `grp`, and kSlices slice blocks in `sl` whose entries are stored
+// group-major, then slice-major, then row-major starting at entry position
+// nz0.  Row pointers of slice blocks go to brp (positions from brp_base);
+// dst[r * kSlices + s] receives the first position of row r's slice s.
+static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int inst, int NB, int64_t nz0,
+                         int64_t brp_base, std::vector<Blk>& grp, std::vector<Blk>& sl,
+                         std::vector<int32_t>& brp, std::vector<int32_t>& dst) {
+  std::vector<std::pair<int64_t, int64_t>> groups;
+  int64_t start = 0;
+  int64_t acc[kSlices] = {0};
+  auto flush = [&](int64_t e) {
+    if (e > start) groups.emplace_back(start, e);
+    start = e;
+    for (int q = 0; q < kSlices; ++q) acc[q] = 0;
+  };
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int32_t* c = cnt + r * kSlices;
+    bool big = false, over = (r - start) >= kMaxRows;
+    for (int q = 0; q < kSlices; ++q) {
+      big |= c[q] > NB;
+      over |= acc[q] + c[q] > NB;
+    }
+    if (big) {
+      flush(r);
+      groups.emplace_back(r, r + 1);
+      start = r + 1;
+      continue;
+    }
+    if (over) flush(r);
+    for (int q = 0; q < kSlices; ++q) acc[q] += c[q];
+  }
+  flush(nrows);
+  if (groups.empty()) groups.emplace_back(0, 0);
+  dst.assign(nrows * kSlices, 0);
+  int64_t pos = nz0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const int64_t a = groups[g].first, e = groups[g].second;
+    Blk ep;
+    ep.r0 = (int32_t)(base + a);
+    ep.r1 = (int32_t)(base + e);
+    ep.inst = inst;
+    ep.meta = blk_meta(BK_STREAM, kSlices, 0);
+    ep.gid = (int32_t)g;
+    ep.rp_off = 0;
+    ep.p0 = 0;
+    ep.pn = 0;
+    grp.push_back(ep);
+    for (int q = 0; q < kSlices; ++q) {
+      Blk k = ep;
+      k.rp_off = (int32_t)(brp_base + (int64_t)brp.size());
+      k.p0 = (int32_t)pos;
+      int64_t mx = 0;
+      for (int64_t r = a; r < e; ++r) {
+        brp.push_back((int32_t)pos);
+        dst[r * kSlices + q] = (int32_t)pos;
+        pos += cnt[r * kSlices + q];
+        mx = std::max<int64_t>(mx, cnt[r * kSlices + q]);
+      }
+      brp.push_back((int32_t)pos);
+      k.pn = (int32_t)(pos - k.p0);
+      k.meta = blk_meta((e - a == 1 && mx > NB) ? BK_LONG : BK_STREAM, kSlices, q);
+      sl.push_back(k);
+    }
+  }
 }
 
 struct Slot {
   bool used = false;
   int64_t n = 0, m = 0, m_eq = 0, nnz = 0;
   int64_t row0 = 0, col0 = 0, nz0 = 0;
-  std::vector<Blk> bP, bD;  // block lists (inst field = slot id)
+  std::vector<Blk> bP, bD;  // one block per row group (inst field = slot id, gid local)
+  std::vector<Blk> bPS, bDS;  // slice blocks of sliced groups (empty when not sliced)
+  int64_t brpP0 = 0, brpPn = 0, brpD0 = 0, brpDn = 0;  // ranges in the brp spaces
   bool watched = false;
   bool reported = false;
 };
@@ -130,7 +212,8 @@ class Engine final : public EngineBase {
  public:
   Engine(const Options& opt, hipStream_t s, int64_t cap_m, int64_t cap_n, int64_t cap_nnz, int slots)
       : opt_(opt), stream_(s), MS_(cap_m), NS_(cap_n), NZ_(cap_nnz), nslots_(slots),
-        am_(cap_m), an_(cap_n), az_(cap_nnz), slots_(slots) {
+        am_(cap_m), an_(cap_n), az_(cap_nnz), abK_(2 * kSlices * cap_m), abKT_(2 * kSlices * cap_n),
+        slots_(slots) {
     try {
       allocate();
     } catch (...) {
@@ -184,6 +267,7 @@ class Engine final : public EngineBase {
   void transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1, const std::vector<Blk>& bD);
   void preprocess(const std::vector<int>& ids, const std::vector<Blk>& nP, const std::vector<Blk>& nD,
                   const std::vector<int4>& nr);
+  void slice_matrix(int id, bool dual);
   IterArgs<T> args() const;
   void pull_states();
 
@@ -191,7 +275,7 @@ class Engine final : public EngineBase {
   hipStream_t stream_;
   int64_t MS_, NS_, NZ_;
   int nslots_;
-  RangeAlloc am_, an_, az_;
+  RangeAlloc am_, an_, az_, abK_, abKT_;
   std::vector<Slot> slots_;
   int64_t g_next_ = 0;  // index of the next step to launch
 
@@ -209,6 +293,11 @@ class Engine final : public EngineBase {
   double *c_o = nullptr, *l_o = nullptr, *u_o = nullptr, *Dc = nullptr, *fn = nullptr;
   T *c = nullptr, *l = nullptr, *u = nullptr, *x = nullptr, *x0 = nullptr, *xbar = nullptr,
     *xT = nullptr, *ktyp = nullptr, *cx1 = nullptr, *cx2 = nullptr;
+  // column-sliced layout
+  int32_t *brpK = nullptr, *brpKT = nullptr;
+  T *spartD = nullptr, *spartP = nullptr;
+  Blk *d_schedPS = nullptr, *d_schedDS = nullptr;
+  int64_t capPS_ = 0, capDS_ = 0, nPS_ = 0, nDS_ = 0;
   // control
   InstState* d_st = nullptr;
   int* d_status = nullptr;
@@ -249,6 +338,8 @@ void Engine<T>::allocate() {
   dalloc(&KT_rp, NS_);
   for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dalloc(p, NS_);
   for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2}) dalloc(p, NS_);
+  dalloc(&brpK, 2 * kSlices * MS_);
+  dalloc(&brpKT, 2 * kSlices * NS_);
   dalloc(&d_st, nslots_);
   dalloc(&d_status, nslots_);
   dalloc(&d_cnt, nslots_);
@@ -289,6 +380,12 @@ void Engine<T>::release_all() {
   dfree(KT_rp);
   for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dfree(*p);
   for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2}) dfree(*p);
+  dfree(brpK);
+  dfree(brpKT);
+  dfree(spartD);
+  dfree(spartP);
+  dfree(d_schedPS);
+  dfree(d_schedDS);
   dfree(d_st);
   dfree(d_status);
   dfree(d_cnt);
@@ -314,6 +411,12 @@ IterArgs<T> Engine<T>::args() const {
   A.KT_rp = KT_rp;
   A.KT_ci = KT_ci;
   A.KT_v = KT_v;
+  A.brpK = brpK;
+  A.brpKT = brpKT;
+  A.spartD = spartD;
+  A.spartP = spartP;
+  A.MS = MS_;
+  A.NS = NS_;
   A.c = c;
   A.l = l;
   A.u = u;
@@ -343,6 +446,8 @@ IterArgs<T> Engine<T>::args() const {
   A.partD = partD;
   A.schedP = d_schedP;
   A.schedD = d_schedD;
+  A.schedPS = d_schedPS;
+  A.schedDS = d_schedDS;
   return A;
 }
 
@@ -644,6 +749,14 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs, bool on_devic
     nr.push_back(r);
   }
   preprocess(ids, nP, nD, nr);
+  // column-slice the matrices whose gathered vector would not stay in one L2
+  for (int id : ids) {
+    const Slot& S = slots_[id];
+    if (opt_.slice_min_bytes >= 0 && S.nnz > 0 && S.n * (int64_t)sizeof(T) > opt_.slice_min_bytes)
+      slice_matrix(id, true);
+    if (opt_.slice_min_bytes >= 0 && S.nnz > 0 && S.m * (int64_t)sizeof(T) > opt_.slice_min_bytes)
+      slice_matrix(id, false);
+  }
   sched_dirty_ = true;
   for (int id : ids) slots_[id].watched = true;
   return ids;
@@ -806,6 +919,81 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
   cleanup();
 }
 
+// Reorders one LP's K (dual = true; slices over its variables) or K^T
+// (slices over its constraints) into the column-sliced layout.
+template <class T>
+void Engine<T>::slice_matrix(int id, bool dual) {
+  constexpr int NB = Tile<T>::NB;
+  Slot& S = slots_[id];
+  const int64_t nrows = dual ? S.m : S.n;
+  const int64_t r0 = dual ? S.row0 : S.col0;
+  const int64_t c0 = dual ? S.col0 : S.row0;
+  const int64_t len = dual ? S.n : S.m;
+  const int32_t* rp = dual ? K_rp : KT_rp;
+  int32_t* ci = dual ? K_ci : KT_ci;
+  T* val = dual ? K_v : KT_v;
+  double* v64 = dual ? K_v64 : KT_v64;
+  if (nrows == 0 || S.nnz == 0) return;
+  int32_t* d_cnt = nullptr;
+  dalloc(&d_cnt, nrows * kSlices);
+  slice_count_kernel<<<nblk(nrows), 256, 0, stream_>>>(rp, ci, r0, nrows, c0, len, d_cnt);
+  std::vector<int32_t> cnt(nrows * kSlices);
+  HIPCHECK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  std::vector<Blk> grp, sl;
+  std::vector<int32_t> brp, dst;
+  RangeAlloc& ab = dual ? abK_ : abKT_;
+  // reserve the worst case first, then return what is unused
+  const int64_t cap = kSlices * (2 * nrows + 1);
+  const int64_t at = ab.alloc(cap);
+  if (at < 0) {
+    dfree(d_cnt);
+    throw Error(-2, "no room for sliced row pointers");
+  }
+  build_sliced(cnt.data(), nrows, r0, id, NB, S.nz0, at, grp, sl, brp, dst);
+  if ((int64_t)brp.size() > cap) throw Error(-3, "sliced row pointer overflow");
+  ab.release(at + (int64_t)brp.size(), cap - (int64_t)brp.size());
+  int32_t* brp_d = dual ? brpK : brpKT;
+  HIPCHECK(hipMemcpyAsync(brp_d + at, brp.data(), sizeof(int32_t) * brp.size(), hipMemcpyHostToDevice, stream_));
+  int32_t* d_dst = nullptr;
+  int32_t* ci2 = nullptr;
+  T* v2 = nullptr;
+  double* v642 = nullptr;
+  dalloc(&d_dst, nrows * kSlices);
+  dalloc(&ci2, S.nnz);
+  dalloc(&v2, S.nnz);
+  if (sizeof(T) != 8) dalloc(&v642, S.nnz);
+  HIPCHECK(hipMemcpyAsync(d_dst, dst.data(), sizeof(int32_t) * dst.size(), hipMemcpyHostToDevice, stream_));
+  // the scatter writes positions nz0..nz0+nnz; shift the temporaries by -nz0
+  slice_scatter_kernel<T><<<nblk(nrows), 256, 0, stream_>>>(rp, ci, val, v64, r0, nrows, c0, len, d_dst,
+                                                            ci2 - S.nz0, v2 - S.nz0,
+                                                            v642 ? v642 - S.nz0 : nullptr);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(ci + S.nz0, ci2, sizeof(int32_t) * S.nnz, hipMemcpyDeviceToDevice, stream_));
+  HIPCHECK(hipMemcpyAsync(val + S.nz0, v2, sizeof(T) * S.nnz, hipMemcpyDeviceToDevice, stream_));
+  if (v642) HIPCHECK(hipMemcpyAsync(v64 + S.nz0, v642, sizeof(double) * S.nnz, hipMemcpyDeviceToDevice, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  dfree(d_cnt);
+  dfree(d_dst);
+  dfree(ci2);
+  dfree(v2);
+  dfree(v642);
+  if (dual) {
+    S.bD = grp;
+    S.bDS = sl;
+    S.brpD0 = at;
+    S.brpDn = (int64_t)brp.size();
+  } else {
+    S.bP = grp;
+    S.bPS = sl;
+    S.brpP0 = at;
+    S.brpPn = (int64_t)brp.size();
+  }
+  // slice partial sums live in space-sized buffers, allocated on first use
+  if (dual && !spartD) dalloc(&spartD, 3 * kSlices * MS_);
+  if (!dual && !spartP) dalloc(&spartP, 3 * kSlices * NS_);
+}
+
 template <class T>
 void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_iter) {
   HIPCHECK(hipStreamSynchronize(stream_));
@@ -848,40 +1036,46 @@ void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_
 
 template <class T>
 void Engine<T>::rebuild_schedules() {
-  std::vector<Blk> P, D;
+  std::vector<Blk> P, D, PS, DS;
   std::vector<int> live;
   std::vector<int4> rg;
+  auto append = [](std::vector<Blk>& dst, const std::vector<Blk>& src, int32_t goff) {
+    for (Blk k : src) {
+      k.gid += goff;
+      dst.push_back(k);
+    }
+  };
   for (int s = 0; s < nslots_; ++s) {
-    if (!slots_[s].used) continue;
+    const Slot& sl = slots_[s];
+    if (!sl.used) continue;
     int4 r;
     r.x = (int)P.size();
-    P.insert(P.end(), slots_[s].bP.begin(), slots_[s].bP.end());
+    append(PS, sl.bPS, r.x);
+    append(P, sl.bP, r.x);
     r.y = (int)P.size();
     r.z = (int)D.size();
-    D.insert(D.end(), slots_[s].bD.begin(), slots_[s].bD.end());
+    append(DS, sl.bDS, r.z);
+    append(D, sl.bD, r.z);
     r.w = (int)D.size();
     live.push_back(s);
     rg.push_back(r);
   }
   HIPCHECK(hipStreamSynchronize(stream_));
-  if ((int64_t)P.size() > capP_) {
-    dfree(d_schedP);
-    dfree(partP);
-    capP_ = std::max<int64_t>((int64_t)P.size(), 2 * capP_);
-    dalloc(&d_schedP, capP_);
-    dalloc(&partP, capP_ * kNS);
-  }
-  if ((int64_t)D.size() > capD_) {
-    dfree(d_schedD);
-    dfree(partD);
-    capD_ = std::max<int64_t>((int64_t)D.size(), 2 * capD_);
-    dalloc(&d_schedD, capD_);
-    dalloc(&partD, capD_ * kNS);
-  }
-  nP_ = (int64_t)P.size();
-  nD_ = (int64_t)D.size();
-  if (nP_) HIPCHECK(hipMemcpyAsync(d_schedP, P.data(), sizeof(Blk) * nP_, hipMemcpyHostToDevice, stream_));
-  if (nD_) HIPCHECK(hipMemcpyAsync(d_schedD, D.data(), sizeof(Blk) * nD_, hipMemcpyHostToDevice, stream_));
+  auto upload = [&](std::vector<Blk>& v, Blk*& d, int64_t& cap, int64_t& n, double** part) {
+    if ((int64_t)v.size() > cap) {
+      dfree(d);
+      if (part) dfree(*part);
+      cap = std::max<int64_t>((int64_t)v.size(), 2 * cap);
+      dalloc(&d, cap);
+      if (part) dalloc(part, cap * kNS);
+    }
+    n = (int64_t)v.size();
+    if (n) HIPCHECK(hipMemcpyAsync(d, v.data(), sizeof(Blk) * n, hipMemcpyHostToDevice, stream_));
+  };
+  upload(P, d_schedP, capP_, nP_, &partP);
+  upload(D, d_schedD, capD_, nD_, &partD);
+  upload(PS, d_schedPS, capPS_, nPS_, nullptr);
+  upload(DS, d_schedDS, capDS_, nDS_, nullptr);
   if (!live.empty()) {
     int* d_ids = nullptr;
     int4* d_rg = nullptr;
@@ -925,8 +1119,10 @@ void Engine<T>::launch_chunk() {
         }
         HIPCHECK(hipEventRecord(e[0], stream_));
       }
+      if (nPS_) slice_step<T><<<(unsigned)nPS_, kThreads, 0, stream_>>>(A, i, 0);
       primal_step<T><<<(unsigned)nP_, kThreads, 0, stream_>>>(A, i);
       if (timed) HIPCHECK(hipEventRecord(e[1], stream_));
+      if (nDS_) slice_step<T><<<(unsigned)nDS_, kThreads, 0, stream_>>>(A, i, 1);
       dual_step<T><<<(unsigned)nD_, kThreads, 0, stream_>>>(A, i);
       if (timed) HIPCHECK(hipEventRecord(e[2], stream_));
     }
@@ -1029,6 +1225,8 @@ void Engine<T>::remove(const std::vector<int>& ids) {
     am_.release(S.row0, S.m + 1);
     an_.release(S.col0, S.n + 1);
     az_.release(S.nz0, S.nnz);
+    abK_.release(S.brpD0, S.brpDn);
+    abKT_.release(S.brpP0, S.brpPn);
     S = Slot();
     h_status[0][id] = h_status[1][id] = 0;
   }

@@ -21,14 +21,32 @@ template <class T> struct Tile { static constexpr int NB = 2048; };
 
 enum Mode : int { M_SKIP = 0, M_NORMAL = 1, M_CHECK = 2, M_EVAL = 3, M_RESID = 4 };
 enum Phase : int { PH_NORMAL = 0, PH_EVAL = 1, PH_RESID = 2 };
-enum BlkKind : int { BK_STREAM = 0, BK_LONG = 1 };
+enum BlkKind : int { BK_STREAM = 0, BK_LONG = 1, BK_PAD = 2 };
+
+// Column slices of a sliced matrix: one per XCD, so that consecutive
+// workgroups (dispatched round-robin over the XCDs) gather from a slice of the
+// vector small enough to stay in that XCD's L2.
+constexpr int kSlices = 8;
 enum Status : int { ST_RUNNING = 0, ST_OPTIMAL = 1, ST_PRIMAL_INFEAS = 2, ST_DUAL_INFEAS = 3,
                     ST_ITER_LIMIT = 4, ST_TIME_LIMIT = 5, ST_NUMERICAL = 6 };
 
-// One workgroup's share of a CSR matrix: rows [r0, r1) (space positions).
+// One workgroup's share of a CSR matrix: rows [r0, r1) (space positions) and
+// the entries [p0, p0 + pn).  A plain block covers whole rows; the blocks of
+// a sliced row group (nsl = kSlices) cover the same rows, block `slice`
+// holding only the entries whose column falls in that slice, with its own
+// row pointers at brp[rp_off].  gid numbers row groups (partial sums and
+// arrival counters); meta packs kind | nsl << 8 | slice << 16.
 struct Blk {
-  int32_t r0, r1, inst, kind;
+  int32_t r0, r1, inst, meta;
+  int32_t gid, rp_off, p0, pn;
 };
+
+__host__ __device__ inline int blk_kind(const Blk& b) { return b.meta & 0xff; }
+__host__ __device__ inline int blk_nsl(const Blk& b) { return (b.meta >> 8) & 0xff; }
+__host__ __device__ inline int blk_slice(const Blk& b) { return (b.meta >> 16) & 0xff; }
+__host__ __device__ inline int32_t blk_meta(int kind, int nsl, int slice) {
+  return kind | (nsl << 8) | (slice << 16);
+}
 
 // Check-step sums (stored in InstState::acc between the check and eval steps).
 enum AccSlot : int {
@@ -41,7 +59,7 @@ struct alignas(16) InstState {
   int64_t row0, col0, nz0;
   int32_t m, m_eq, n, reflect;
   int32_t C, primal_weight;
-  int32_t pb0, pb1, db0, db1;        // this instance's blocks in the primal / dual schedules
+  int32_t pb0, pb1, db0, db1;        // this instance's row groups (gids) in the primal / dual schedules
   double tol, eps_inf, beta, artificial, eta, qnorm, cnorm;
   int64_t max_iter;
   // dynamic state

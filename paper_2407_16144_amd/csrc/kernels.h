@@ -15,6 +15,8 @@ struct IterArgs {
   const int32_t* KT_rp;
   const int32_t* KT_ci;
   const T* KT_v;
+  const int32_t* brpK;   // row pointers of sliced blocks of K / K^T
+  const int32_t* brpKT;
   // n-space
   const T* c;
   const T* l;
@@ -38,6 +40,10 @@ struct IterArgs {
   T* kxp;    // K x+ at the last eval
   T* cy1;    // primal-infeasibility ray candidates (clamped)
   T* cy2;
+  // slice partial row sums of sliced row groups: [3][kSlices][space]
+  T* spartD;   // m-space (dual step)
+  T* spartP;   // n-space (primal step)
+  int64_t MS, NS;
   // control
   InstState* st;
   const int64_t* gbase;
@@ -45,8 +51,10 @@ struct IterArgs {
   int* status_out;
   double* partP;
   double* partD;
-  const Blk* schedP;
+  const Blk* schedP;   // one block per row group (primal / dual step kernels)
   const Blk* schedD;
+  const Blk* schedPS;  // slice blocks of sliced row groups (slice kernel)
+  const Blk* schedDS;
 };
 
 }  // namespace halp

@@ -83,8 +83,19 @@ __device__ __forceinline__ int group_size(int nrows) {
   return g;
 }
 
+// Workgroup barrier that orders LDS only: outstanding global loads (prefetched
+// epilogue operands) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // block SpMV: row sums of NV gathered vectors for the rows of one block.
+// rp points at the block's row pointers (rp[0..nrows], entry positions);
+// the entry range [b.p0, b.p0 + b.pn) comes with the descriptor, so entry
+// loads start without waiting for the row pointers.
 // Stream blocks (<= NB entries, <= kMaxRows rows): entries are loaded once,
 // coalesced, into registers; per gathered vector the products go to LDS and
 // groups of G lanes reduce each row.  Long blocks (one row): strided loop
@@ -100,27 +111,27 @@ __device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const i
   constexpr int NB = Tile<T>::NB;
   const int tid = threadIdx.x;
   const int nrows = b.r1 - b.r0;
-  if (b.kind == BK_LONG) {
-    const int p0 = rp[b.r0], p1 = rp[b.r0 + 1];
+  const int p0 = b.p0, pn = b.pn;
+  if (blk_kind(b) == BK_LONG) {
     T acc[NV][4];
 #pragma unroll
     for (int a = 0; a < NV; ++a)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[a][u] = (T)0;
-    int e = p0 + tid;
-    for (; e + 3 * kThreads < p1; e += 4 * kThreads) {
+    int e = tid;
+    for (; e + 3 * kThreads < pn; e += 4 * kThreads) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int c = ci[e + u * kThreads];
-        const T v = val[e + u * kThreads];
+        const int c = ci[p0 + e + u * kThreads];
+        const T v = val[p0 + e + u * kThreads];
         acc[0][u] += v * s0[c];
         if constexpr (NV > 1) acc[1][u] += v * s1[c];
         if constexpr (NV > 2) acc[2][u] += v * s2[c];
       }
     }
-    for (; e < p1; e += kThreads) {
-      const int c = ci[e];
-      const T v = val[e];
+    for (; e < pn; e += kThreads) {
+      const int c = ci[p0 + e];
+      const T v = val[p0 + e];
       acc[0][0] += v * s0[c];
       if constexpr (NV > 1) acc[1][0] += v * s1[c];
       if constexpr (NV > 2) acc[2][0] += v * s2[c];
@@ -128,27 +139,34 @@ __device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const i
 #pragma unroll
     for (int a = 0; a < NV; ++a) {
       T t = (acc[a][0] + acc[a][1]) + (acc[a][2] + acc[a][3]);
-      t = block_sum1(t, s_red);
-      if (tid == 0) s_rsum[a][0] = (a == 0) ? t * scale0 : t;
+      t = wave_sum(t);
+      if ((tid & 63) == 0) s_red[tid >> 6][a] = (double)t;
     }
-    __syncthreads();
+    lds_barrier();
+    if (tid == 0) {
+#pragma unroll
+      for (int a = 0; a < NV; ++a) {
+        T t = (T)s_red[0][a];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) t += (T)s_red[w][a];
+        s_rsum[a][0] = (a == 0) ? t * scale0 : t;
+      }
+    }
+    lds_barrier();
     return;
   }
-  for (int i = tid; i <= nrows; i += kThreads) s_rp[i] = rp[b.r0 + i];
-  __syncthreads();
-  const int p0 = s_rp[0];
-  const int nnz = s_rp[nrows] - p0;
   constexpr int EPT = NB / kThreads;
   int cidx[EPT];
   T v[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int e = tid + k * kThreads;
-    if (e < nnz) {
+    if (e < pn) {
       cidx[k] = ci[p0 + e];
       v[k] = val[p0 + e];
     }
   }
+  for (int i = tid; i <= nrows; i += kThreads) s_rp[i] = rp[i] - p0;
   const int G = group_size(nrows);
   const int lane = tid & (G - 1);
   const int rpb = kThreads / G;  // rows per pass
@@ -158,20 +176,38 @@ __device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const i
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int e = tid + k * kThreads;
-      if (e < nnz) s_prod[e] = v[k] * src[cidx[k]];
+      if (e < pn) s_prod[e] = v[k] * src[cidx[k]];
     }
-    __syncthreads();
+    lds_barrier();
     for (int base = 0; base < nrows; base += rpb) {
       const int r = base + tid / G;
       T acc = (T)0;
       if (r < nrows) {
-        const int q1 = s_rp[r + 1] - p0;
-        for (int q = s_rp[r] - p0 + lane; q < q1; q += G) acc += s_prod[q];
+        const int q1 = s_rp[r + 1];
+        for (int q = s_rp[r] + lane; q < q1; q += G) acc += s_prod[q];
       }
       for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
       if (lane == 0 && r < nrows) s_rsum[a][r] = (a == 0) ? acc * scale0 : acc;
     }
-    __syncthreads();
+    lds_barrier();
+  }
+}
+
+// Row sums of a sliced row group: the kSlices partial sums written by the
+// slice kernel, added in slice order.
+template <class T, int NV>
+__device__ __forceinline__ void gather_slices(const Blk& b, const T* __restrict__ spart, int64_t space,
+                                              T (*s_rsum)[kMaxRows]) {
+  const int nrows = b.r1 - b.r0;
+  const int t = threadIdx.x;
+  if (t < nrows) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+      T acc = (T)0;
+#pragma unroll
+      for (int q = 0; q < kSlices; ++q) acc += spart[(int64_t)(a * kSlices + q) * space + b.r0 + t];
+      s_rsum[a][t] = acc;
+    }
   }
 }
 
@@ -217,19 +253,36 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
   const int64_t g = *A.gbase + step;
   const int mode = step_mode(S, g);
   if (mode == M_SKIP) return;
-  if (mode == M_EVAL)
-    block_spmv<T, 3>(b, A.KT_rp, A.KT_ci, A.KT_v, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
-  else if (mode != M_RESID)
-    block_spmv<T, 1>(b, A.KT_rp, A.KT_ci, A.KT_v, A.y, A.y, A.y, s_prod, s_rsum, s_rp, s_red);
+  const int nrows = b.r1 - b.r0;
+  const int t = threadIdx.x;
+  const bool own = t < nrows;
+  const int64_t j = (int64_t)b.r0 + (own ? t : 0);
+  const bool resid = (mode == M_RESID);
+  // epilogue operands, loaded before the SpMV so their latency overlaps it
+  T cj = 0, lj = 0, uj = 0, xo = 0, x0j = 0, kty = 0;
+  if (own) {
+    cj = A.c[j];
+    lj = A.l[j];
+    uj = A.u[j];
+    if (mode != M_EVAL) {
+      xo = resid ? A.xT[j] : A.x[j];
+      x0j = resid ? xo : A.x0[j];
+      if (resid) kty = A.ktyp[j];
+    }
+  }
+  if (blk_nsl(b) > 1) {
+    if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartP, A.NS, s_rsum);
+    else if (!resid) gather_slices<T, 1>(b, A.spartP, A.NS, s_rsum);
+  } else if (mode == M_EVAL) {
+    block_spmv<T, 3>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+  } else if (!resid) {
+    block_spmv<T, 1>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, A.y, A.y, A.y, s_prod, s_rsum, s_rp, s_red);
+  }
 
   double ps[kNS];
 #pragma unroll
   for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
-  const int nrows = b.r1 - b.r0;
-  const int t = threadIdx.x;
-  if (t < nrows) {
-    const int64_t j = (int64_t)b.r0 + t;
-    const T cj = A.c[j], lj = A.l[j], uj = A.u[j];
+  if (own) {
     const bool lf = isfinite(lj), uf = isfinite(uj);
     if (mode == M_EVAL) {
       const T g0 = s_rsum[0][t];
@@ -253,13 +306,10 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
         ps[2 * a + 1] = vv * vv;
       }
     } else {
-      const bool resid = (mode == M_RESID);
-      const T xo = resid ? A.xT[j] : A.x[j];
-      const T kty = resid ? A.ktyp[j] : s_rsum[0][t];
+      if (!resid) kty = s_rsum[0][t];
       const T tau = (T)S.tau;
       const T xp = clampT<T>(xo - tau * (cj - kty), lj, uj);
       const T xb = (T)2 * xp - xo;
-      const T x0j = resid ? xo : A.x0[j];
       const int64_t k = g - S.kbase;
       const double w = (double)(k + 1) / (double)(k + 2);
       const T xh = S.reflect ? xb : xp;
@@ -288,8 +338,43 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
   }
   if (mode != M_NORMAL) {
     block_sum_ns(ps, s_red, s_out);
-    if (t < kNS) A.partP[(int64_t)blockIdx.x * kNS + t] = s_out[t];
+    if (t < kNS) A.partP[(int64_t)b.gid * kNS + t] = s_out[t];
   }
+}
+
+// Partial row sums of one column slice of a sliced row group (written to
+// spart for the step kernel of the same step to add up).  dual = 1: rows of
+// K gathering xbar (or xT, cx1, cx2 at an eval step); dual = 0: rows of K^T
+// gathering y (or yT, cy1, cy2).
+template <class T>
+__global__ __launch_bounds__(kThreads) void slice_step(IterArgs<T> A, int step, int dual) {
+  __shared__ T s_prod[Tile<T>::NB];
+  __shared__ T s_rsum[3][kMaxRows];
+  __shared__ int s_rp[kMaxRows + 1];
+  __shared__ double s_red[kThreads / 64][kNS];
+  const Blk b = (dual ? A.schedDS : A.schedPS)[blockIdx.x];
+  if (blk_kind(b) == BK_PAD) return;
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP || (!dual && mode == M_RESID)) return;
+  const int32_t* rp = (dual ? A.brpK : A.brpKT) + b.rp_off;
+  const int32_t* ci = dual ? A.K_ci : A.KT_ci;
+  const T* val = dual ? A.K_v : A.KT_v;
+  T* spart = dual ? A.spartD : A.spartP;
+  const int64_t space = dual ? A.MS : A.NS;
+  const int nv = mode == M_EVAL ? 3 : 1;
+  if (mode == M_EVAL) {
+    if (dual) block_spmv<T, 3>(b, rp, ci, val, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    else block_spmv<T, 3>(b, rp, ci, val, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+  } else {
+    const T* src = dual ? A.xbar : A.y;
+    block_spmv<T, 1>(b, rp, ci, val, src, src, src, s_prod, s_rsum, s_rp, s_red);
+  }
+  const int nrows = b.r1 - b.r0;
+  const int sl = blk_slice(b);
+  for (int r = threadIdx.x; r < nrows; r += kThreads)
+    for (int a = 0; a < nv; ++a) spart[(int64_t)(a * kSlices + sl) * space + b.r0 + r] = s_rsum[a][r];
 }
 
 // ---------------------------------------------------------------------------
@@ -406,20 +491,35 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
   const int64_t g = *A.gbase + step;
   const int mode = step_mode(S, g);
   if (mode == M_SKIP) return;
-  if (mode == M_EVAL)
-    block_spmv<T, 3>(b, A.K_rp, A.K_ci, A.K_v, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
-  else
-    block_spmv<T, 1>(b, A.K_rp, A.K_ci, A.K_v, A.xbar, A.xbar, A.xbar, s_prod, s_rsum, s_rp, s_red);
+  const int nrows = b.r1 - b.r0;
+  const int t = threadIdx.x;
+  const bool own = t < nrows;
+  const int64_t i = (int64_t)b.r0 + (own ? t : 0);
+  const bool resid = (mode == M_RESID);
+  // epilogue operands, loaded before the SpMV so their latency overlaps it
+  T qi = 0, yo = 0, y0i = 0, kxpi = 0;
+  if (own) {
+    qi = A.q[i];
+    if (mode != M_EVAL) {
+      yo = resid ? A.yT[i] : A.y[i];
+      y0i = resid ? yo : A.y0[i];
+      if (resid) kxpi = A.kxp[i];
+    }
+  }
+  if (blk_nsl(b) > 1) {
+    if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartD, A.MS, s_rsum);
+    else gather_slices<T, 1>(b, A.spartD, A.MS, s_rsum);
+  } else if (mode == M_EVAL) {
+    block_spmv<T, 3>(b, A.K_rp + b.r0, A.K_ci, A.K_v, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+  } else {
+    block_spmv<T, 1>(b, A.K_rp + b.r0, A.K_ci, A.K_v, A.xbar, A.xbar, A.xbar, s_prod, s_rsum, s_rp, s_red);
+  }
 
   double ps[kNS];
 #pragma unroll
   for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
-  const int nrows = b.r1 - b.r0;
-  const int t = threadIdx.x;
-  if (t < nrows) {
-    const int64_t i = (int64_t)b.r0 + t;
+  if (own) {
     const bool ineq = (i - S.row0) >= S.m_eq;
-    const T qi = A.q[i];
     if (mode == M_EVAL) {
       const T s0 = s_rsum[0][t];
       A.kxp[i] = s0;
@@ -439,14 +539,11 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
         }
       }
     } else {
-      const bool resid = (mode == M_RESID);
       const T s0 = s_rsum[0][t];
-      const T yo = resid ? A.yT[i] : A.y[i];
       const T sigma = (T)S.sigma;
       T yp = yo + sigma * (qi - s0);
       if (ineq) yp = fmax(yp, (T)0);
       const T yb = (T)2 * yp - yo;
-      const T y0i = resid ? yo : A.y0[i];
       const int64_t k = g - S.kbase;
       const double w = (double)(k + 1) / (double)(k + 2);
       const T yh = S.reflect ? yb : yp;
@@ -455,7 +552,7 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
         A.y0[i] = yo;
         const double d = (double)yo - (double)yp;
         ps[0] = d * d;
-        ps[1] = d * (0.5 * ((double)A.kxp[i] - (double)s0));
+        ps[1] = d * (0.5 * ((double)kxpi - (double)s0));
       } else if (mode == M_CHECK) {
         A.yT[i] = yp;
         const T dyv = yo - yp;
@@ -480,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
   if (mode == M_NORMAL) return;
 
   block_sum_ns(ps, s_red, s_out);
-  if (t < kNS) A.partD[(int64_t)blockIdx.x * kNS + t] = s_out[t];
+  if (t < kNS) A.partD[(int64_t)b.gid * kNS + t] = s_out[t];
   __threadfence();
   __syncthreads();
   if (t == 0) {
@@ -516,7 +613,7 @@ __global__ __launch_bounds__(kThreads) void row_factor_kernel(const Blk* sched, 
   const Blk b = sched[blockIdx.x];
   const int tid = threadIdx.x;
   const int nrows = b.r1 - b.r0;
-  if (b.kind == BK_LONG) {
+  if (blk_kind(b) == BK_LONG) {
     const int p0 = rp[b.r0], p1 = rp[b.r0 + 1];
     double a = 0.0;
     for (int e = p0 + tid; e < p1; e += kThreads) {
@@ -579,7 +676,7 @@ __global__ __launch_bounds__(kThreads) void scale_values_kernel(const Blk* sched
   const Blk b = sched[blockIdx.x];
   const int nrows = b.r1 - b.r0;
   const int tid = threadIdx.x;
-  const int G = (b.kind == BK_LONG) ? kThreads : group_size(nrows);
+  const int G = (blk_kind(b) == BK_LONG) ? kThreads : group_size(nrows);
   const int lane = tid & (G - 1);
   for (int base = 0; base < nrows; base += kThreads / G) {
     const int r = base + tid / G;
@@ -732,7 +829,7 @@ __global__ __launch_bounds__(kThreads) void pw_forward_kernel(const Blk* schedD,
   const Blk b = schedD[blockIdx.x];
   const InstState& S = st[b.inst];
   if (S.pw_done) return;
-  block_spmv<double, 1>(b, rp, ci, val, w, w, w, s_prod, s_rsum, s_rp, s_red, S.pw_scale);
+  block_spmv<double, 1>(b, rp + b.r0, ci, val, w, w, w, s_prod, s_rsum, s_rp, s_red, S.pw_scale);
   const int nrows = b.r1 - b.r0;
   if ((int)threadIdx.x < nrows) u[(int64_t)b.r0 + threadIdx.x] = s_rsum[0][threadIdx.x];
 }
@@ -750,7 +847,7 @@ __global__ __launch_bounds__(kThreads) void pw_backward_kernel(const Blk* schedP
   const Blk b = schedP[blockIdx.x];
   const InstState& S = st[b.inst];
   if (S.pw_done) return;
-  block_spmv<double, 1>(b, rp, ci, val, u, u, u, s_prod, s_rsum, s_rp, s_red);
+  block_spmv<double, 1>(b, rp + b.r0, ci, val, u, u, u, s_prod, s_rsum, s_rp, s_red);
   double v[kNS];
   for (int s = 0; s < kNS; ++s) v[s] = 0.0;
   const int nrows = b.r1 - b.r0;
@@ -822,7 +919,7 @@ __global__ __launch_bounds__(kThreads) void row_ids_kernel(const Blk* sched, con
                                                            int64_t z0, int32_t* rowid) {
   const Blk b = sched[blockIdx.x];
   const int nrows = b.r1 - b.r0;
-  const int G = (b.kind == BK_LONG) ? kThreads : group_size(nrows);
+  const int G = (blk_kind(b) == BK_LONG) ? kThreads : group_size(nrows);
   const int lane = threadIdx.x & (G - 1);
   for (int base = 0; base < nrows; base += kThreads / G) {
     const int r = base + threadIdx.x / G;
@@ -830,6 +927,40 @@ __global__ __launch_bounds__(kThreads) void row_ids_kernel(const Blk* sched, con
     const int row = b.r0 + r;
     const int p1 = rp[row + 1];
     for (int e = rp[row] + lane; e < p1; e += G) rowid[e - z0] = row;
+  }
+}
+
+// cnt[(r - r0) * kSlices + s] = entries of row r whose column lies in slice s
+// of the gathered range [c0, c0 + len)
+__global__ void slice_count_kernel(const int32_t* rp, const int32_t* ci, int64_t r0, int64_t nrows,
+                                   int64_t c0, int64_t len, int32_t* cnt) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int32_t c[kSlices];
+  for (int q = 0; q < kSlices; ++q) c[q] = 0;
+  for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
+    const int q = (int)(((int64_t)(ci[e] - c0) * kSlices) / len);
+    c[q] += 1;
+  }
+  for (int q = 0; q < kSlices; ++q) cnt[r * kSlices + q] = c[q];
+}
+
+// Scatter row r's entries to their slice-major positions: dst[(r - r0) *
+// kSlices + s] is the first position of row r's slice-s entries.
+template <class V>
+__global__ void slice_scatter_kernel(const int32_t* rp, const int32_t* ci, const V* val, const double* v64,
+                                     int64_t r0, int64_t nrows, int64_t c0, int64_t len, const int32_t* dst,
+                                     int32_t* ci_out, V* val_out, double* v64_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int32_t d[kSlices];
+  for (int q = 0; q < kSlices; ++q) d[q] = dst[r * kSlices + q];
+  for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
+    const int q = (int)(((int64_t)(ci[e] - c0) * kSlices) / len);
+    const int32_t p = d[q]++;
+    ci_out[p] = ci[e];
+    val_out[p] = val[e];
+    if (v64_out) v64_out[p] = v64[e];
   }
 }
 
@@ -940,6 +1071,8 @@ template __global__ void primal_step<double>(IterArgs<double>, int);
 template __global__ void primal_step<float>(IterArgs<float>, int);
 template __global__ void dual_step<double>(IterArgs<double>, int);
 template __global__ void dual_step<float>(IterArgs<float>, int);
+template __global__ void slice_step<double>(IterArgs<double>, int, int);
+template __global__ void slice_step<float>(IterArgs<float>, int, int);
 template __global__ void cast_kernel<float>(const double*, float*, int64_t);
 template __global__ void scale_primal_kernel<double>(const Blk*, const double*, const double*,
                                                      const double*, const double*, double*, double*,
@@ -948,6 +1081,12 @@ template __global__ void scale_primal_kernel<float>(const Blk*, const double*, c
                                                     const double*, const double*, float*, float*, float*);
 template __global__ void scale_dual_kernel<double>(const Blk*, const double*, const double*, double*);
 template __global__ void scale_dual_kernel<float>(const Blk*, const double*, const double*, float*);
+template __global__ void slice_scatter_kernel<double>(const int32_t*, const int32_t*, const double*,
+                                                      const double*, int64_t, int64_t, int64_t, int64_t,
+                                                      const int32_t*, int32_t*, double*, double*);
+template __global__ void slice_scatter_kernel<float>(const int32_t*, const int32_t*, const float*,
+                                                     const double*, int64_t, int64_t, int64_t, int64_t,
+                                                     const int32_t*, int32_t*, float*, double*);
 template __global__ void transpose_gather_kernel<double>(const int32_t*, const int32_t*, const double*,
                                                          int64_t, int64_t, int32_t*, double*);
 template __global__ void init_primal_kernel<double>(const Blk*, const double*, const double*, double*,

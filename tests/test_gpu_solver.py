@@ -258,3 +258,72 @@ def test_iteration_limit_and_errors():
             halp.lp_solve(h, 1e-4, 100_000)       # one solve per handle
     finally:
         halp.lp_destroy(h)
+
+
+# ------------------------------------------------------------------ column-sliced layout
+
+@pytest.mark.parametrize("name,code", METHODS)
+def test_sliced_layout_trajectory_parity(name, code):
+    """K and K^T stored column-sliced (one slice per XCD, forced on a small LP):
+    the slice partial sums are added in a fixed order, so trajectories still
+    agree with the oracle to 1e-10."""
+    lp = lpgen.scaled_powerlaw(21, 500, 1800)
+    print(f"case sliced trajectory {name}", flush=True)
+    res, x, y, _ = _gpu(lp, 0.0, 1000, method=code, slice_min_bytes=0)
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=0.0, max_iter=1000))
+    assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
+    assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
+
+
+def test_sliced_layout_certificates():
+    lp = lpgen.add_contradictory_rows(lpgen.tiny(5), seed=1)
+    print("case sliced primal infeasible", flush=True)
+    res, x, y, ray = _gpu(lp, 1e-8, 200_000, slice_min_bytes=0)
+    assert res["status"] == halp.LP_PRIMAL_INFEASIBLE
+    assert oracle.primal_ray_check(lp, ray)[0]
+    lp = lpgen.add_unbounded_column(lpgen.scaled_powerlaw(6, 40, 120), seed=2)
+    print("case sliced dual infeasible", flush=True)
+    res, x, y, ray = _gpu(lp, 1e-8, 200_000, slice_min_bytes=0)
+    assert res["status"] == halp.LP_DUAL_INFEASIBLE
+    assert oracle.dual_ray_check(lp, ray)[0]
+
+
+def test_sliced_long_rows():
+    """A row whose share of one column slice exceeds a stream tile (2048
+    entries) takes the long-block path of the slice kernel."""
+    base = lpgen.scaled_powerlaw(9, 400, 30000)
+    rng = np.random.default_rng(5)
+    dense_cols = np.sort(rng.choice(base.n, 20000, replace=False)).astype(np.int32)
+    vals = rng.standard_normal(20000)
+    xs = base.meta["x_plant"]
+    rp = base.rowptr.astype(np.int64)
+    me = base.m_eq
+    col = np.concatenate([base.col[:rp[me]], dense_cols, base.col[rp[me]:]])
+    val = np.concatenate([base.val[:rp[me]], vals, base.val[rp[me]:]])
+    rowptr = np.concatenate([rp[:me + 1], rp[me:] + 20000]).astype(np.int32)
+    rhs = np.concatenate([base.rhs[:me], [vals @ xs[dense_cols]], base.rhs[me:]])
+    lp = lpgen.LP(base.n, me + 1, base.m_ineq, rowptr, col, val, base.c, rhs, base.lb, base.ub)
+    print("case sliced long row", flush=True)
+    P = core.scaled_problem(lp)
+    s, _ = oracle.power_iteration(P.K, 0)
+    res, x, y, _ = _gpu(lp, 0.0, 320, eta=0.9 / s, slice_min_bytes=0)
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=320, eta=0.9 / s))
+    assert res["iters"] == ref.iters
+    assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
+
+
+def test_sliced_batch_equals_single():
+    lps = [lpgen.scaled_powerlaw(300 + i, m, 3 * m) for i, m in enumerate([60, 500, 20])]
+    print("case sliced batch", flush=True)
+    opt = halp.lp_default_options(slice_min_bytes=0)
+    h = halp.lp_batch_create(lps, opt=opt)
+    try:
+        halp.lp_batch_solve(h, 1e-6, 100_000)
+        for i, lp in enumerate(lps):
+            rb = halp.lp_batch_status(h, i).as_dict()
+            xb, yb = halp.lp_batch_get_solution(h, i, lp.n, lp.m)
+            rs, xs, ys, _ = halp.solve_lp(lp, tol=1e-6, max_iter=100_000, opt=opt)
+            assert rb["iters"] == rs["iters"]
+            assert np.array_equal(xb, xs) and np.array_equal(yb, ys)
+    finally:
+        halp.lp_batch_destroy(h)
