@@ -63,6 +63,162 @@ def cpu_baseline(lp, eta, gpu_iters, gpu_power_iters, method, budget_s=30.0):
             "seconds_per_iteration": t_iter}
 
 
+def _opts(halp, args, **kw):
+    return halp.lp_default_options(
+        method=halp.LP_METHOD_R2HPDHG if args.method == "r2hpdhg" else halp.LP_METHOD_RHPDHG,
+        precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64, **kw)
+
+
+def _pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, max(0, math.ceil(q * len(v)) - 1))]
+
+
+def serial_solve(halp, lps, tol, max_iter):
+    """One LP at a time, FP64 rHPDHG, device-resident inputs: the baseline the
+    batched and serving paths are compared with."""
+    opt = halp.lp_default_options(method=halp.LP_METHOD_RHPDHG)
+    t0 = time.perf_counter()
+    solved = 0
+    for lp in lps:
+        r, *_ = halp.solve_lp(lp, tol=tol, max_iter=max_iter, opt=opt, on_device=True)
+        solved += r["status"] in (1, 2, 3)
+    return solved, time.perf_counter() - t0
+
+
+def run_batch(args):
+    """512 power-law LPs of uneven size (10% primal infeasible) solved as one
+    batch: per step, create (device-resident inputs) + solve of all of them."""
+    import torch
+    import lpgen
+    import paper_2407_16144_amd as halp
+    lps = lpgen.batch(count=args.batch_count)
+    nnz = sum(lp.nnz for lp in lps)
+    arr, keep = halp.make_problems(lps, on_device=True)
+    torch.cuda.synchronize()
+    opt = _opts(halp, args, profile=args.profile_every)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        h = halp.lp_batch_create_from(arr, len(lps), True, stream=stream, opt=opt)
+        try:
+            halp.lp_batch_solve(h, args.tol, args.max_iter, args.time_limit)
+            res = [halp.lp_batch_status(h, i).as_dict() for i in range(len(lps))]
+            kt = halp.lp_batch_kernel_times(h)
+        finally:
+            halp.lp_batch_destroy(h)
+        return res, kt
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = []
+    kp = kd = 0.0
+    kn = 0
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        res, kt = step()
+        lat.append(time.perf_counter() - s0)
+        kp, kd, kn = kp + kt[0], kd + kt[1], kn + kt[2]
+        st = [r["status"] for r in res]
+        print(f"batch step {i}: {lat[-1]:.2f}s optimal={st.count(1)} infeasible={st.count(2)} "
+              f"limit={st.count(4)}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solved = sum(r["status"] in (1, 2, 3) for r in res) * args.steps
+    s = 8 if args.precision == "fp64" else 4
+    bytes_step = sum(sum(algorithmic_bytes(lp.n, lp.m, lp.nnz, s)) for lp in lps)
+    tstep = (kp + kd) / max(kn, 1)
+    ach = bytes_step / (tstep * 1e-3) / 1e9 if tstep > 0 else 0.0
+    out = {"metric": "solved LPs/s + p99 latency at 1e-4 rel. KKT; SpMV HBM GB/s vs peak",
+           "value": round(solved / wall, 3), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": f"batch of {len(lps)} power-law LPs, {nnz} nnz total, tol {args.tol:g}",
+                      "method": args.method, "precision": args.precision,
+                      "max_iters": max(r["iters"] for r in res),
+                      "p50_latency_s": round(_pct(lat, 0.5), 3), "p99_latency_s": round(_pct(lat, 0.99), 3)},
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "primal_step+dual_step (whole step)", "timed_steps": kn}}
+    if args.serial_baseline:
+        k = min(args.serial_baseline, len(lps))
+        sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)
+        out["serial_fp64_rhpdhg"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
+                                     "value": round(sv / sw, 3), "unit": "LPs/s"}
+    del keep
+    return out
+
+
+def run_serve(args):
+    """Continuous batching: Poisson arrivals (rate LP/s) of batched-size LPs
+    with 2% large, 5% primal-infeasible and 2% dual-infeasible ones, replayed
+    against the server; latency = completion - arrival."""
+    import lpgen
+    import paper_2407_16144_amd as halp
+    trace = lpgen.serving_trace(count=args.requests, rate=args.rate)
+    t_gen = time.perf_counter()
+    lps = [lpgen.request_instance(r) for r in trace]
+    print(f"generated {len(lps)} requests in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    opt = _opts(halp, args, use_graph=0)
+    h = halp.lp_server_create(int(args.budget_gb * 1e9), 512, opt=opt)
+    try:
+        t0 = halp.lp_server_clock(h)
+        arrivals = [t0 + r.t_arrival for r in trace]
+        tickets = {}
+        nxt = 0
+        done = {}
+        last_print = 0.0
+        while len(done) < len(trace):
+            now = halp.lp_server_clock(h)
+            while nxt < len(trace) and arrivals[nxt] <= now:
+                tickets[halp.lp_server_submit(h, lps[nxt], args.tol, args.max_iter, arrivals[nxt])] = nxt
+                nxt += 1
+            q, live, _ = halp.lp_server_info(h)
+            if live == 0 and q == 0:
+                time.sleep(max(0.0, min(0.002, arrivals[nxt] - now)) if nxt < len(trace) else 0)
+                continue
+            halp.lp_server_step(h, 1)
+            for tk, idx in list(tickets.items()):
+                r, td = halp.lp_server_poll(h, tk)
+                if r is not None:
+                    done[idx] = (r.as_dict(), td)
+                    halp.lp_server_release(h, tk)
+                    del tickets[tk]
+            if now - last_print > 5.0:
+                last_print = now
+                print(f"t={now - t0:.1f}s submitted={nxt} done={len(done)} queued={q} live={live}",
+                      file=sys.stderr, flush=True)
+        t_end = max(td for _, td in done.values())
+    finally:
+        halp.lp_server_destroy(h)
+    lat = [done[i][1] - arrivals[i] for i in range(len(trace))]
+    solved = sum(done[i][0]["status"] in (1, 2, 3) for i in range(len(trace)))
+    span = t_end - arrivals[0]
+    kinds = {}
+    for i, r in enumerate(trace):
+        kinds.setdefault(r.kind, []).append(done[i][0]["status"])
+    out = {"metric": "solved LPs/s + p99 latency at 1e-4 rel. KKT; SpMV HBM GB/s vs peak",
+           "value": round(solved / span, 3), "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": round(1e3 * span, 1), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",
+           "data": "synthetic",
+           "config": {"workload": f"serving: {len(trace)} Poisson arrivals at {args.rate:g} LP/s, tol {args.tol:g}",
+                      "method": args.method, "precision": args.precision,
+                      "p50_latency_s": round(_pct(lat, 0.5), 4), "p99_latency_s": round(_pct(lat, 0.99), 4),
+                      "solved": solved, "requests": len(trace),
+                      "status_by_kind": {k: {str(s): v.count(s) for s in set(v)} for k, v in kinds.items()}}}
+    if args.serial_baseline:
+        k = min(args.serial_baseline, len(lps))
+        sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)
+        out["serial_fp64_rhpdhg"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
+                                     "value": round(sv / sw, 3), "unit": "LPs/s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +229,13 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
     ap.add_argument("--time-limit", type=float, default=600.0)
-    ap.add_argument("--workload", default="large", choices=["large", "tiny"])
+    ap.add_argument("--workload", default="large", choices=["large", "mixed", "tiny", "batch", "serve"])
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--requests", type=int, default=1200)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--serial-baseline", type=int, default=0,
+                    help="batch/serve: also solve the first N LPs one at a time (FP64 rHPDHG)")
     ap.add_argument("--profile-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
@@ -90,6 +252,10 @@ def main():
     import paper_2407_16144_amd as halp
 
     torch.cuda.set_device(0)
+    if args.workload in ("batch", "serve"):
+        out = run_batch(args) if args.workload == "batch" else run_serve(args)
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_probe_mb > 0:
         nel = int(args.copy_probe_mb * 1e6 / 8)
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -98,7 +264,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(f"copy probe: {nel * 8} bytes read and written per launch", file=sys.stderr, flush=True)
-    lp = lpgen.large_single() if args.workload == "large" else lpgen.tiny()
+    lp = {"large": lpgen.large_single, "mixed": lpgen.large_mixed, "tiny": lpgen.tiny}[args.workload]()
     dev = torch.device("cuda", 0)
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
     tens = (T(lp.rowptr, torch.int32), T(lp.col, torch.int32), T(lp.val, torch.float64),

@@ -97,6 +97,10 @@ typedef struct {
   int64_t slice_min_bytes;  /* store K (K^T) column-sliced, one slice per XCD, when
                                the vector its product gathers exceeds this many
                                bytes (default 2 MiB; < 0 never) */
+  double polish_tol;        /* FP32 precision: when the requested tolerance is
+                               below this (default 1e-6), solve in FP32 to this
+                               tolerance, then continue in FP64 from the FP32
+                               candidate (same scaling and step) to the request */
   int verbose;
 } lp_options;
 
@@ -111,6 +115,7 @@ typedef struct {
   double rel_primal, rel_dual, rel_gap;
   double omega, eta, sigma_hat;
   int power_iters;
+  int64_t polish_iters;     /* FP64 iterations after an FP32 phase (0 if none) */
   double seconds;           /* wall time of the last lp_solve / batch solve */
 } lp_result;
 

@@ -42,7 +42,8 @@ class lp_options(C.Structure):
                 ("power_rtol", C.c_double), ("eps_infeas", C.c_double),
                 ("primal_weight", C.c_int), ("seed", C.c_uint64), ("eta", C.c_double),
                 ("omega0", C.c_double), ("chunk", C.c_int), ("use_graph", C.c_int),
-                ("profile", C.c_int), ("slice_min_bytes", C.c_int64), ("verbose", C.c_int)]
+                ("profile", C.c_int), ("slice_min_bytes", C.c_int64), ("polish_tol", C.c_double),
+                ("verbose", C.c_int)]
 
 
 class lp_result(C.Structure):
@@ -51,7 +52,7 @@ class lp_result(C.Structure):
                 ("dobj", C.c_double), ("rel_kkt", C.c_double), ("rel_primal", C.c_double),
                 ("rel_dual", C.c_double), ("rel_gap", C.c_double), ("omega", C.c_double),
                 ("eta", C.c_double), ("sigma_hat", C.c_double), ("power_iters", C.c_int),
-                ("seconds", C.c_double)]
+                ("polish_iters", C.c_int64), ("seconds", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -205,16 +206,33 @@ def lp_destroy(h):
     _lib.lp_destroy(h)
 
 
-def make_problems(lps):
-    """An lp_problem array (and the arrays it points into) for lpgen.LP-like objects."""
+def make_problems(lps, on_device=False):
+    """An lp_problem array (and the arrays it points into) for lpgen.LP-like
+    objects; with on_device the arrays are copied to GPU tensors first."""
     arr = (lp_problem * len(lps))()
     keep = []
     for i, lp in enumerate(lps):
-        ptrs, k = _marshal_problem(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, lp.c,
-                                   lp.rhs, lp.lb, lp.ub, 0)
-        keep.append(k)
+        if on_device:
+            t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to("cuda")
+            arrays = (t(lp.rowptr, torch.int32), t(lp.col, torch.int32), t(lp.val, torch.float64),
+                      t(lp.c, torch.float64), t(lp.rhs, torch.float64), t(lp.lb, torch.float64),
+                      t(lp.ub, torch.float64))
+            ptrs = [a.data_ptr() if a.numel() else None for a in arrays]
+            keep.append(arrays)
+        else:
+            ptrs, k = _marshal_problem(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, lp.c,
+                                       lp.rhs, lp.lb, lp.ub, 0)
+            keep.append(k)
         arr[i] = lp_problem(lp.n, lp.m_eq, lp.m_ineq, *ptrs)
     return arr, keep
+
+
+def lp_batch_create_from(arr, count, on_device, stream=None, opt=None):
+    """lp_batch_create over an existing lp_problem array."""
+    h = C.c_void_p()
+    _check(_lib.lp_batch_create(C.byref(h), count, arr, int(on_device), stream,
+                                C.byref(opt) if opt is not None else None))
+    return h
 
 
 def lp_batch_create(lps, stream=None, opt=None):

@@ -59,6 +59,7 @@ halp::Options to_opts(const lp_options* o) {
   r.use_graph = o->use_graph;
   r.profile = o->profile;
   r.slice_min_bytes = o->slice_min_bytes;
+  r.polish_tol = o->polish_tol;
   r.verbose = o->verbose;
   return r;
 }
@@ -151,12 +152,81 @@ double now_s() {
 
 }  // namespace
 
+// Copy of an LP's inputs kept by FP32 handles for the FP64 polish phase
+// (host vectors for host inputs, device buffers for device inputs).
+struct RawLP {
+  bool on_device = false;
+  int64_t n = 0, m_eq = 0, m_ineq = 0, nnz = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> val, c, rhs, lb, ub;
+  void* dmem = nullptr;
+  lp_problem view{};
+  void capture(const lp_problem& p, int64_t nz, bool dev, hipStream_t s) {
+    on_device = dev;
+    n = p.n;
+    m_eq = p.m_eq;
+    m_ineq = p.m_ineq;
+    nnz = nz;
+    const int64_t m = m_eq + m_ineq;
+    if (!dev) {
+      rp.assign(p.row_ptr, p.row_ptr + m + 1);
+      if (nz) {
+        ci.assign(p.col_idx, p.col_idx + nz);
+        val.assign(p.val, p.val + nz);
+      }
+      c.assign(p.c, p.c + n);
+      lb.assign(p.lb, p.lb + n);
+      ub.assign(p.ub, p.ub + n);
+      if (m) rhs.assign(p.rhs, p.rhs + m);
+      view = lp_problem{n, m_eq, m_ineq, rp.data(), ci.data(), val.data(), c.data(), rhs.data(),
+                        lb.data(), ub.data()};
+      return;
+    }
+    const size_t bytes = 4 * (m + 1) + 12 * nz + 8 * (3 * n + m) + 64;
+    if (hipMalloc(&dmem, bytes) != hipSuccess) throw halp::Error(LP_ERR_OOM, "device allocation failed");
+    char* q = (char*)dmem;
+    auto take = [&](size_t b) {
+      char* r = q;
+      q += (b + 7) & ~size_t(7);
+      return (void*)r;
+    };
+    int32_t* drp = (int32_t*)take(4 * (m + 1));
+    int32_t* dci = (int32_t*)take(4 * nz);
+    double* dval = (double*)take(8 * nz);
+    double* dc = (double*)take(8 * n);
+    double* drhs = (double*)take(8 * m);
+    double* dlb = (double*)take(8 * n);
+    double* dub = (double*)take(8 * n);
+    auto cp = [&](void* d, const void* src, size_t b) {
+      if (b && hipMemcpyAsync(d, src, b, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        throw halp::Error(LP_ERR_DEVICE, "device copy failed");
+    };
+    cp(drp, p.row_ptr, 4 * (m + 1));
+    cp(dci, p.col_idx, 4 * nz);
+    cp(dval, p.val, 8 * nz);
+    cp(dc, p.c, 8 * n);
+    cp(drhs, p.rhs, 8 * m);
+    cp(dlb, p.lb, 8 * n);
+    cp(dub, p.ub, 8 * n);
+    view = lp_problem{n, m_eq, m_ineq, drp, dci, dval, dc, drhs, dlb, dub};
+  }
+  ~RawLP() {
+    if (dmem) (void)hipFree(dmem);
+  }
+};
+
 struct lp_solver {
   StreamHolder stream;
+  halp::Options opt;
   std::unique_ptr<halp::EngineBase> eng;
   int id = -1;
   bool solved = false;
   double seconds = 0.0;
+  // FP32 mode: inputs kept for the FP64 polish, and the polish engine
+  std::unique_ptr<RawLP> raw;
+  std::unique_ptr<halp::EngineBase> eng64;
+  int id64 = -1;
+  halp::Result first;  // result of the FP32 phase when polished
 };
 
 struct lp_batch {
@@ -192,6 +262,7 @@ void lp_default_options(lp_options* o) {
   o->use_graph = d.use_graph;
   o->profile = d.profile;
   o->slice_min_bytes = d.slice_min_bytes;
+  o->polish_tol = d.polish_tol;
   o->verbose = d.verbose;
 }
 
@@ -210,8 +281,13 @@ int lp_create(lp_solver** out, int64_t n, int64_t m_eq, int64_t m_ineq, const in
     if (!inputs_on_device) halp::validate_host_problem(to_problem(p));
     std::unique_ptr<lp_solver> s(new lp_solver());
     s->stream.init(stream);
+    s->opt = o;
     s->eng = halp::make_engine(o, s->stream.s, m_eq + m_ineq + 1, n + 1, nnz, 1);
     s->id = s->eng->add({to_problem(p)}, inputs_on_device != 0)[0];
+    if (o.precision == 1 && o.polish_tol > 0.0) {
+      s->raw.reset(new RawLP());
+      s->raw->capture(p, nnz, inputs_on_device != 0, s->stream.s);
+    }
     *out = s.release();
     return LP_OK;
   });
@@ -223,8 +299,38 @@ int lp_solve(lp_solver* s, double tol, int64_t max_iter, double time_limit_s) {
     if (s->solved) return fail(LP_ERR_STATE, "this handle has already solved its LP");
     if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
     const double t0 = now_s();
-    s->eng->set_params({s->id}, tol, max_iter);
+    const bool polish = s->raw && tol < s->opt.polish_tol;
+    s->eng->set_params({s->id}, polish ? s->opt.polish_tol : tol, max_iter);
     s->eng->run(time_limit_s);
+    if (polish) {
+      // FP64 polish from the FP32 candidate, unless the FP32 phase already
+      // ended for good (infeasible, time limit)
+      const halp::Result r = s->eng->result(s->id);
+      const bool go = r.status == LP_OPTIMAL || r.status == LP_ITER_LIMIT || r.status == LP_NUMERICAL;
+      const double left = time_limit_s < 0 ? -1.0 : time_limit_s - (now_s() - t0);
+      if (go && r.iters < max_iter && (time_limit_s < 0 || left > 0)) {
+        halp::Options o64 = s->opt;
+        o64.precision = 0;
+        const lp_problem& p = s->raw->view;
+        s->eng64 = halp::make_engine(o64, s->stream.s, p.m_eq + p.m_ineq + 1, p.n + 1, s->raw->nnz, 1);
+        s->id64 = s->eng64->add({to_problem(p)}, s->raw->on_device)[0];
+        double* buf = nullptr;
+        if (hipMalloc((void**)&buf, sizeof(double) * (p.n + p.m_eq + p.m_ineq + 1)) != hipSuccess)
+          throw halp::Error(LP_ERR_OOM, "device allocation failed");
+        double omega = 1.0;
+        try {
+          s->eng->export_point(s->id, buf, buf + p.n, &omega);
+          s->eng64->import_point(s->id64, buf, buf + p.n, omega);
+        } catch (...) {
+          (void)hipFree(buf);
+          throw;
+        }
+        (void)hipFree(buf);
+        s->first = r;
+        s->eng64->set_params({s->id64}, tol, max_iter - r.iters);
+        s->eng64->run(left);
+      }
+    }
     s->seconds = now_s() - t0;
     s->solved = true;
     return LP_OK;
@@ -234,7 +340,15 @@ int lp_solve(lp_solver* s, double tol, int64_t max_iter, double time_limit_s) {
 int lp_status(const lp_solver* s, lp_result* out) {
   return guarded([&]() -> int {
     if (!s || !out) return fail(LP_ERR_INVALID, "null argument");
-    *out = to_result(s->eng->result(s->id), s->seconds);
+    if (s->eng64) {
+      *out = to_result(s->eng64->result(s->id64), s->seconds);
+      out->polish_iters = out->iters;
+      out->iters += s->first.iters;
+      out->restarts += s->first.restarts;
+      out->checks += s->first.checks;
+    } else {
+      *out = to_result(s->eng->result(s->id), s->seconds);
+    }
     return LP_OK;
   });
 }
@@ -243,7 +357,8 @@ int lp_get_solution(const lp_solver* s, double* x, double* y, int to_device) {
   return guarded([&]() -> int {
     if (!s) return fail(LP_ERR_INVALID, "null handle");
     if (!s->solved) return fail(LP_ERR_STATE, "solve first");
-    s->eng->solution(s->id, x, y, to_device != 0);
+    if (s->eng64) s->eng64->solution(s->id64, x, y, to_device != 0);
+    else s->eng->solution(s->id, x, y, to_device != 0);
     return LP_OK;
   });
 }
@@ -252,7 +367,8 @@ int lp_get_certificate(const lp_solver* s, double* ray, int to_device) {
   return guarded([&]() -> int {
     if (!s || !ray) return fail(LP_ERR_INVALID, "null argument");
     if (!s->solved) return fail(LP_ERR_STATE, "solve first");
-    s->eng->certificate(s->id, ray, to_device != 0);
+    if (s->eng64) s->eng64->certificate(s->id64, ray, to_device != 0);
+    else s->eng->certificate(s->id, ray, to_device != 0);
     return LP_OK;
   });
 }
@@ -462,17 +578,12 @@ int lp_server_submit(lp_server* s, const lp_problem* p, double tol, int64_t max_
 int lp_server_step(lp_server* s, int chunks, int* n_done) {
   return guarded([&]() -> int {
     if (!s || chunks < 0) return fail(LP_ERR_INVALID, "bad argument");
-    // admission: every queued LP that fits, in arrival order
-    std::vector<halp::Problem> ps;
-    std::vector<int64_t> tk;
-    std::deque<int64_t> rest;
-    int free_slots = s->max_slots - s->eng->live();
-    for (int64_t t : s->queue) {
-      Request& r = s->reqs.at(t);
-      const int64_t m = r.m_eq + r.m_ineq;
-      // conservative: the engine checks each space for one LP at a time, so
-      // admit one by one
-      if ((int)ps.size() < free_slots && s->eng->fits(r.n, m, r.nnz)) {
+    // admission: the longest prefix of the FIFO queue that fits, preprocessed together
+    if (!s->queue.empty() && s->eng->live() < s->max_slots) {
+      std::vector<halp::Problem> ps;
+      for (int64_t t : s->queue) {
+        if ((int)ps.size() >= s->max_slots - s->eng->live()) break;
+        Request& r = s->reqs.at(t);
         halp::Problem q;
         q.n = r.n;
         q.m_eq = r.m_eq;
@@ -484,17 +595,20 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
         q.rhs = r.rhs.data();
         q.lb = r.lb.data();
         q.ub = r.ub.data();
-        std::vector<int> id = s->eng->add({q}, false);
-        s->eng->set_params(id, r.tol, r.max_iter);
-        r.slot = id[0];
-        s->slot_ticket[id[0]] = t;
         ps.push_back(q);
-        tk.push_back(t);
-      } else {
-        rest.push_back(t);
       }
+      std::vector<int> ids = s->eng->add(ps, false, true);
+      std::map<std::pair<double, int64_t>, std::vector<int>> by_params;
+      for (size_t k = 0; k < ids.size(); ++k) {
+        const int64_t t = s->queue.front();
+        s->queue.pop_front();
+        Request& r = s->reqs.at(t);
+        by_params[{r.tol, r.max_iter}].push_back(ids[k]);
+        r.slot = ids[k];
+        s->slot_ticket[ids[k]] = t;
+      }
+      for (auto& kv : by_params) s->eng->set_params(kv.second, kv.first.first, kv.first.second);
     }
-    s->queue.swap(rest);
     int nd = 0;
     if (s->eng->live() > 0 && chunks > 0) {
       std::vector<int> done = s->eng->advance(chunks);

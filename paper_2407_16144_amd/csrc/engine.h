@@ -46,7 +46,8 @@ struct Options {
   int chunk = 64;
   int use_graph = 1;
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
-  int64_t slice_min_bytes = 2 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
+  int64_t slice_min_bytes = 2 << 20;
+  double polish_tol = 1e-6;  // fp32: solve to this tolerance in fp32, then polish in fp64  // column-slice a matrix whose gathered vector is larger (< 0: never)
   int verbose = 0;
 };
 
@@ -73,8 +74,9 @@ class Error : public std::runtime_error {
 class EngineBase {
  public:
   virtual ~EngineBase() = default;
-  // add LPs (validated, preprocessed, iterates initialised); returns slot ids
-  virtual std::vector<int> add(const std::vector<Problem>& probs, bool on_device) = 0;
+  // add LPs (validated, preprocessed, iterates initialised); returns slot ids.
+  // partial: admit the longest prefix that fits instead of failing.
+  virtual std::vector<int> add(const std::vector<Problem>& probs, bool on_device, bool partial = false) = 0;
   virtual void set_params(const std::vector<int>& ids, double tol, int64_t max_iter) = 0;
   // run until every listed slot has terminated (or the time limit)
   virtual void run(double time_limit_s) = 0;
@@ -92,6 +94,11 @@ class EngineBase {
   virtual int64_t footprint(int64_t n, int64_t m, int64_t nnz) const = 0;
   virtual bool fits(int64_t n, int64_t m, int64_t nnz) const = 0;
   virtual KernelTimes kernel_times() const = 0;
+  // last check candidate T(z) in the scaled space, as float64 device arrays
+  virtual void export_point(int id, double* x, double* y, double* omega) = 0;
+  // start the next solve of `id` from (x, y) (scaled, float64 device arrays)
+  // with primal weight omega: iterate and anchor both set to the point
+  virtual void import_point(int id, const double* x, const double* y, double omega) = 0;
 };
 
 // Host-side validation of a host-memory LP (throws Error(-1, ...)); needs no GPU.

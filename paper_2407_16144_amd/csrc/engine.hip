@@ -249,7 +249,7 @@ class Engine final : public EngineBase {
     return free_slots > 0 && am_.can(m + 1) && an_.can(n + 1) && az_.can(nnz);
   }
 
-  std::vector<int> add(const std::vector<Problem>& probs, bool on_device) override;
+  std::vector<int> add(const std::vector<Problem>& probs, bool on_device, bool partial) override;
   void set_params(const std::vector<int>& ids, double tol, int64_t max_iter) override;
   void run(double time_limit_s) override;
   std::vector<int> advance(int chunks) override;
@@ -257,6 +257,8 @@ class Engine final : public EngineBase {
   Result result(int id) override;
   void solution(int id, double* x, double* y, bool to_device) override;
   void certificate(int id, double* ray, bool to_device) override;
+  void export_point(int id, double* x, double* y, double* omega) override;
+  void import_point(int id, const double* x, const double* y, double omega) override;
 
  private:
   void allocate();
@@ -566,7 +568,8 @@ void Engine<T>::transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1,
 }
 
 template <class T>
-std::vector<int> Engine<T>::add(const std::vector<Problem>& probs, bool on_device) {
+std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_device, bool partial) {
+  std::vector<Problem> probs(probs_in);
   constexpr int NB = Tile<T>::NB;
   std::vector<int> ids;
   HIPCHECK(hipStreamSynchronize(stream_));
@@ -629,13 +632,17 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs, bool on_devic
           id = s;
           break;
         }
-      if (id < 0) throw Error(-2, "no free LP slot");
+      if (id < 0) {
+        if (partial) break;
+        throw Error(-2, "no free LP slot");
+      }
       const int64_t r0 = am_.alloc(m + 1);
       const int64_t c0 = r0 < 0 ? -1 : an_.alloc(p.n + 1);
       const int64_t z0 = c0 < 0 ? -1 : az_.alloc(nnzs[k]);
       if (r0 < 0 || c0 < 0 || z0 < 0) {
         if (r0 >= 0) am_.release(r0, m + 1);
         if (c0 >= 0) an_.release(c0, p.n + 1);
+        if (partial) break;
         throw Error(-2, "not enough device memory reserved for this LP");
       }
       if (z0 + nnzs[k] > INT32_MAX) throw Error(-1, "more than 2^31 stored entries");
@@ -663,6 +670,13 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs, bool on_devic
     throw;
   }
 
+  if (ids.size() < probs.size()) {
+    probs.resize(ids.size());
+    canon.resize(ids.size());
+    use_canon.resize(ids.size());
+    nnzs.resize(ids.size());
+  }
+  if (ids.empty()) return ids;
   // 2. upload (K values in FP64, row pointers / columns shifted to space positions)
   std::vector<std::vector<int32_t>> host_rp(probs.size());
   for (size_t k = 0; k < probs.size(); ++k) {
@@ -1299,6 +1313,45 @@ void Engine<T>::certificate(int id, double* ray, bool to_device) {
                           stream_));
   HIPCHECK(hipStreamSynchronize(stream_));
   dfree(tmp);
+}
+
+template <class T>
+void Engine<T>::export_point(int id, double* xo, double* yo, double* omega) {
+  if (id < 0 || id >= nslots_ || !slots_[id].used) throw Error(-1, "invalid LP id");
+  const Slot& S = slots_[id];
+  copy_state_kernel<T><<<nblk(S.n), 256, 0, stream_>>>(xT, xo, S.col0, S.n);
+  if (S.m) copy_state_kernel<T><<<nblk(S.m), 256, 0, stream_>>>(yT, yo, S.row0, S.m);
+  HIPCHECK(hipGetLastError());
+  InstState st;
+  HIPCHECK(hipMemcpyAsync(&st, d_st + id, sizeof(InstState), hipMemcpyDeviceToHost, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  *omega = st.omega;
+}
+
+template <class T>
+void Engine<T>::import_point(int id, const double* xi, const double* yi, double omega) {
+  if (id < 0 || id >= nslots_ || !slots_[id].used) throw Error(-1, "invalid LP id");
+  const Slot& S = slots_[id];
+  load_point_kernel<T><<<nblk(S.n), 256, 0, stream_>>>(xi, x, x0, S.col0, S.n);
+  if (S.m) load_point_kernel<T><<<nblk(S.m), 256, 0, stream_>>>(yi, y, y0, S.row0, S.m);
+  HIPCHECK(hipGetLastError());
+  InstState st;
+  HIPCHECK(hipMemcpyAsync(&st, d_st + id, sizeof(InstState), hipMemcpyDeviceToHost, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  st.omega = omega;
+  st.tau = st.eta / omega;
+  st.sigma = st.eta * omega;
+  InstState* d_src = nullptr;
+  int* d_ids = nullptr;
+  dalloc(&d_src, 1);
+  dalloc(&d_ids, 1);
+  HIPCHECK(hipMemcpyAsync(d_src, &st, sizeof(InstState), hipMemcpyHostToDevice, stream_));
+  HIPCHECK(hipMemcpyAsync(d_ids, &id, sizeof(int), hipMemcpyHostToDevice, stream_));
+  write_states_kernel<<<1, 256, 0, stream_>>>(d_st, d_status, d_cnt, d_ids, d_src, 1);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(stream_));
+  dfree(d_src);
+  dfree(d_ids);
 }
 
 std::unique_ptr<EngineBase> make_engine(const Options& opt, hipStream_t stream, int64_t cap_m, int64_t cap_n,

@@ -103,12 +103,34 @@ __device__ __forceinline__ void lds_barrier() {
 // Result: s_rsum[a][r - b.r0].
 // ---------------------------------------------------------------------------
 
+template <class T>
+struct TileRegs {
+  static constexpr int EPT = Tile<T>::NB / kThreads;
+  int cidx[EPT];
+  T v[EPT];
+};
+
+// Loads a stream block's entries (coalesced) into registers; independent of
+// the step mode, so callers issue it before reading the LP state.
+template <class T>
+__device__ __forceinline__ void load_tile(const Blk& b, const int32_t* __restrict__ ci,
+                                          const T* __restrict__ val, TileRegs<T>& R) {
+  if (blk_kind(b) != BK_STREAM) return;
+#pragma unroll
+  for (int k = 0; k < TileRegs<T>::EPT; ++k) {
+    const int e = (int)threadIdx.x + k * kThreads;
+    if (e < b.pn) {
+      R.cidx[k] = ci[b.p0 + e];
+      R.v[k] = val[b.p0 + e];
+    }
+  }
+}
+
 template <class T, int NV>
-__device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           const T* __restrict__ val, const T* __restrict__ s0, const T* __restrict__ s1,
-                           const T* __restrict__ s2, T* s_prod, T (*s_rsum)[kMaxRows], int* s_rp,
-                           double (*s_red)[kNS], T scale0 = (T)1) {
-  constexpr int NB = Tile<T>::NB;
+__device__ void block_spmv_regs(const Blk& b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                const T* __restrict__ val, const TileRegs<T>& R, const T* __restrict__ s0,
+                                const T* __restrict__ s1, const T* __restrict__ s2, T* s_prod,
+                                T (*s_rsum)[kMaxRows], int* s_rp, double (*s_red)[kNS], T scale0 = (T)1) {
   const int tid = threadIdx.x;
   const int nrows = b.r1 - b.r0;
   const int p0 = b.p0, pn = b.pn;
@@ -155,17 +177,7 @@ __device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const i
     lds_barrier();
     return;
   }
-  constexpr int EPT = NB / kThreads;
-  int cidx[EPT];
-  T v[EPT];
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = tid + k * kThreads;
-    if (e < pn) {
-      cidx[k] = ci[p0 + e];
-      v[k] = val[p0 + e];
-    }
-  }
+  constexpr int EPT = TileRegs<T>::EPT;
   for (int i = tid; i <= nrows; i += kThreads) s_rp[i] = rp[i] - p0;
   const int G = group_size(nrows);
   const int lane = tid & (G - 1);
@@ -176,7 +188,7 @@ __device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const i
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int e = tid + k * kThreads;
-      if (e < pn) s_prod[e] = v[k] * src[cidx[k]];
+      if (e < pn) s_prod[e] = R.v[k] * src[R.cidx[k]];
     }
     lds_barrier();
     for (int base = 0; base < nrows; base += rpb) {
@@ -191,6 +203,17 @@ __device__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp, const i
     }
     lds_barrier();
   }
+}
+
+template <class T, int NV>
+__device__ __forceinline__ void block_spmv(const Blk& b, const int32_t* __restrict__ rp,
+                                           const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                           const T* __restrict__ s0, const T* __restrict__ s1,
+                                           const T* __restrict__ s2, T* s_prod, T (*s_rsum)[kMaxRows],
+                                           int* s_rp, double (*s_red)[kNS], T scale0 = (T)1) {
+  TileRegs<T> R;
+  load_tile<T>(b, ci, val, R);
+  block_spmv_regs<T, NV>(b, rp, ci, val, R, s0, s1, s2, s_prod, s_rsum, s_rp, s_red, scale0);
 }
 
 // Row sums of a sliced row group: the kSlices partial sums written by the
@@ -249,34 +272,40 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
   __shared__ double s_out[kNS];
 
   const Blk b = A.schedP[blockIdx.x];
-  const InstState& S = A.st[b.inst];
-  const int64_t g = *A.gbase + step;
-  const int mode = step_mode(S, g);
-  if (mode == M_SKIP) return;
   const int nrows = b.r1 - b.r0;
   const int t = threadIdx.x;
   const bool own = t < nrows;
   const int64_t j = (int64_t)b.r0 + (own ? t : 0);
-  const bool resid = (mode == M_RESID);
-  // epilogue operands, loaded before the SpMV so their latency overlaps it
+  // entries and epilogue operands are loaded before the LP state is read,
+  // so their latency overlaps the state loads (none depends on the mode)
+  TileRegs<T> R;
+  load_tile<T>(b, A.KT_ci, A.KT_v, R);
   T cj = 0, lj = 0, uj = 0, xo = 0, x0j = 0, kty = 0;
   if (own) {
     cj = A.c[j];
     lj = A.l[j];
     uj = A.u[j];
-    if (mode != M_EVAL) {
-      xo = resid ? A.xT[j] : A.x[j];
-      x0j = resid ? xo : A.x0[j];
-      if (resid) kty = A.ktyp[j];
-    }
+    xo = A.x[j];
+    x0j = A.x0[j];
+  }
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP) return;
+  const bool resid = (mode == M_RESID);
+  if (resid && own) {
+    xo = A.xT[j];
+    x0j = xo;
+    kty = A.ktyp[j];
   }
   if (blk_nsl(b) > 1) {
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartP, A.NS, s_rsum);
     else if (!resid) gather_slices<T, 1>(b, A.spartP, A.NS, s_rsum);
   } else if (mode == M_EVAL) {
-    block_spmv<T, 3>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+    block_spmv_regs<T, 3>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp,
+                          s_red);
   } else if (!resid) {
-    block_spmv<T, 1>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, A.y, A.y, A.y, s_prod, s_rsum, s_rp, s_red);
+    block_spmv_regs<T, 1>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.y, A.y, A.y, s_prod, s_rsum, s_rp, s_red);
   }
 
   double ps[kNS];
@@ -354,22 +383,24 @@ __global__ __launch_bounds__(kThreads) void slice_step(IterArgs<T> A, int step, 
   __shared__ double s_red[kThreads / 64][kNS];
   const Blk b = (dual ? A.schedDS : A.schedPS)[blockIdx.x];
   if (blk_kind(b) == BK_PAD) return;
+  const int32_t* rp = (dual ? A.brpK : A.brpKT) + b.rp_off;
+  const int32_t* ci = dual ? A.K_ci : A.KT_ci;
+  const T* val = dual ? A.K_v : A.KT_v;
+  TileRegs<T> R;
+  load_tile<T>(b, ci, val, R);
   const InstState& S = A.st[b.inst];
   const int64_t g = *A.gbase + step;
   const int mode = step_mode(S, g);
   if (mode == M_SKIP || (!dual && mode == M_RESID)) return;
-  const int32_t* rp = (dual ? A.brpK : A.brpKT) + b.rp_off;
-  const int32_t* ci = dual ? A.K_ci : A.KT_ci;
-  const T* val = dual ? A.K_v : A.KT_v;
   T* spart = dual ? A.spartD : A.spartP;
   const int64_t space = dual ? A.MS : A.NS;
   const int nv = mode == M_EVAL ? 3 : 1;
   if (mode == M_EVAL) {
-    if (dual) block_spmv<T, 3>(b, rp, ci, val, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
-    else block_spmv<T, 3>(b, rp, ci, val, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+    if (dual) block_spmv_regs<T, 3>(b, rp, ci, val, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    else block_spmv_regs<T, 3>(b, rp, ci, val, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
   } else {
     const T* src = dual ? A.xbar : A.y;
-    block_spmv<T, 1>(b, rp, ci, val, src, src, src, s_prod, s_rsum, s_rp, s_red);
+    block_spmv_regs<T, 1>(b, rp, ci, val, R, src, src, src, s_prod, s_rsum, s_rp, s_red);
   }
   const int nrows = b.r1 - b.r0;
   const int sl = blk_slice(b);
@@ -487,32 +518,37 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
   __shared__ int s_last;
 
   const Blk b = A.schedD[blockIdx.x];
-  const InstState& S = A.st[b.inst];
-  const int64_t g = *A.gbase + step;
-  const int mode = step_mode(S, g);
-  if (mode == M_SKIP) return;
   const int nrows = b.r1 - b.r0;
   const int t = threadIdx.x;
   const bool own = t < nrows;
   const int64_t i = (int64_t)b.r0 + (own ? t : 0);
-  const bool resid = (mode == M_RESID);
-  // epilogue operands, loaded before the SpMV so their latency overlaps it
+  // entries and epilogue operands are loaded before the LP state is read
+  TileRegs<T> R;
+  load_tile<T>(b, A.K_ci, A.K_v, R);
   T qi = 0, yo = 0, y0i = 0, kxpi = 0;
   if (own) {
     qi = A.q[i];
-    if (mode != M_EVAL) {
-      yo = resid ? A.yT[i] : A.y[i];
-      y0i = resid ? yo : A.y0[i];
-      if (resid) kxpi = A.kxp[i];
-    }
+    yo = A.y[i];
+    y0i = A.y0[i];
+  }
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP) return;
+  const bool resid = (mode == M_RESID);
+  if (resid && own) {
+    yo = A.yT[i];
+    y0i = yo;
+    kxpi = A.kxp[i];
   }
   if (blk_nsl(b) > 1) {
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartD, A.MS, s_rsum);
     else gather_slices<T, 1>(b, A.spartD, A.MS, s_rsum);
   } else if (mode == M_EVAL) {
-    block_spmv<T, 3>(b, A.K_rp + b.r0, A.K_ci, A.K_v, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    block_spmv_regs<T, 3>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
   } else {
-    block_spmv<T, 1>(b, A.K_rp + b.r0, A.K_ci, A.K_v, A.xbar, A.xbar, A.xbar, s_prod, s_rsum, s_rp, s_red);
+    block_spmv_regs<T, 1>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xbar, A.xbar, A.xbar, s_prod, s_rsum, s_rp,
+                          s_red);
   }
 
   double ps[kNS];
@@ -1018,6 +1054,15 @@ __global__ void unscale_kernel(const T* v, const double* D, int64_t off, int64_t
 }
 
 template <class T>
+__global__ void load_point_kernel(const double* src, T* v, T* v0, int64_t off, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    v[off + i] = (T)src[i];
+    v0[off + i] = (T)src[i];
+  }
+}
+
+template <class T>
 __global__ void copy_state_kernel(const T* src, double* dst, int64_t off, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (double)src[off + i];
@@ -1096,6 +1141,8 @@ template __global__ void init_dual_kernel<double>(const Blk*, double*, double*);
 template __global__ void init_dual_kernel<float>(const Blk*, float*, float*);
 template __global__ void unscale_kernel<double>(const double*, const double*, int64_t, int64_t, double*);
 template __global__ void unscale_kernel<float>(const float*, const double*, int64_t, int64_t, double*);
+template __global__ void load_point_kernel<double>(const double*, double*, double*, int64_t, int64_t);
+template __global__ void load_point_kernel<float>(const double*, float*, float*, int64_t, int64_t);
 template __global__ void copy_state_kernel<double>(const double*, double*, int64_t, int64_t);
 template __global__ void copy_state_kernel<float>(const float*, double*, int64_t, int64_t);
 

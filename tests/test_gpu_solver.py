@@ -327,3 +327,59 @@ def test_sliced_batch_equals_single():
             assert np.array_equal(xb, xs) and np.array_equal(yb, ys)
     finally:
         halp.lp_batch_destroy(h)
+
+
+@pytest.mark.parametrize("on_device", [False, True])
+def test_fp32_with_fp64_polish(on_device):
+    """FP32 phase to the polish tolerance, then FP64 from the FP32 candidate."""
+    lp = lpgen.tiny(12)
+    print(f"case fp32 polish device={on_device}", flush=True)
+    opt = halp.lp_default_options(precision=halp.LP_PREC_FP32, polish_tol=1e-5)
+    res, x, y, _ = halp.solve_lp(lp, tol=1e-9, max_iter=500_000, opt=opt, on_device=on_device)
+    assert res["status"] == halp.LP_OPTIMAL
+    assert 0 < res["polish_iters"] < res["iters"]
+    kkt, parts = oracle.rel_kkt(lp, x, y)
+    assert kkt <= 1e-9 * (1 + 1e-6), parts
+    ref = oracle.solve(lp, oracle.Options(tol=1e-9))
+    assert abs(res["pobj"] - ref.pobj) <= 1e-8 * (1 + abs(ref.pobj))
+
+
+def test_server_results_equal_single_results():
+    """Continuous batching: LPs submitted at different times, admitted as
+    memory frees up, give the same result as solving each alone."""
+    lps = [lpgen.scaled_powerlaw(400 + i, m, 3 * m) for i, m in enumerate([50, 400, 120, 900, 30, 250])]
+    lps.append(lpgen.add_contradictory_rows(lpgen.tiny(8), seed=3))
+    lps.append(lpgen.add_unbounded_column(lpgen.scaled_powerlaw(6, 40, 120), seed=2))
+    print("case server", flush=True)
+    opt = halp.lp_default_options(use_graph=0)
+    # a budget that holds only a few of these at once, and 3 slots
+    h = halp.lp_server_create(40_000_000, 3, opt=opt)
+    try:
+        tickets = []
+        for k, lp in enumerate(lps):
+            tickets.append(halp.lp_server_submit(h, lp, 1e-6, 200_000, float(k)))
+            halp.lp_server_step(h, 1)
+        pending = set(tickets)
+        res = {}
+        for _ in range(100_000):
+            if not pending:
+                break
+            halp.lp_server_step(h, 4)
+            q, live, used = halp.lp_server_info(h)
+            assert live <= 3
+            for t in list(pending):
+                r, td = halp.lp_server_poll(h, t)
+                if r is not None:
+                    k = tickets.index(t)
+                    x, y = halp.lp_server_get_solution(h, t, lps[k].n, lps[k].m)
+                    res[k] = (r.as_dict(), x, y)
+                    halp.lp_server_release(h, t)
+                    pending.discard(t)
+        assert not pending
+    finally:
+        halp.lp_server_destroy(h)
+    for k, lp in enumerate(lps):
+        rs, xs, ys, _ = _gpu(lp, 1e-6, 200_000, use_graph=0)
+        rb, xb, yb = res[k]
+        assert rb["status"] == rs["status"] and rb["iters"] == rs["iters"], (k, rb, rs)
+        assert np.array_equal(xb, xs) and np.array_equal(yb, ys), k
