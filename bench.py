@@ -237,6 +237,7 @@ def main():
     ap.add_argument("--serial-baseline", type=int, default=0,
                     help="batch/serve: also solve the first N LPs one at a time (FP64 rHPDHG)")
     ap.add_argument("--profile-every", type=int, default=8)
+    ap.add_argument("--verbose", type=int, default=20, help="library progress line every N seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
                     help="also run a plain device copy of this many MB (counter calibration)")
@@ -274,7 +275,7 @@ def main():
     opt = halp.lp_default_options(
         method=halp.LP_METHOD_R2HPDHG if args.method == "r2hpdhg" else halp.LP_METHOD_RHPDHG,
         precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64,
-        profile=args.profile_every)
+        profile=args.profile_every, verbose=args.verbose)
 
     def step():
         h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,

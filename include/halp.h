@@ -101,7 +101,7 @@ typedef struct {
                                below this (default 1e-6), solve in FP32 to this
                                tolerance, then continue in FP64 from the FP32
                                candidate (same scaling and step) to the request */
-  int verbose;
+  int verbose;              /* k > 0: progress line on stderr every k seconds of a solve */
 } lp_options;
 
 typedef struct {

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -127,12 +128,13 @@ static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int ins
 }
 
 // Column-sliced schedule of one LP's rows.  cnt[r * kSlices + s] counts row
-// r's entries in column slice s.  Rows are grouped so that every slice of a
-// group holds at most NB entries (a row with more gets a group of its own and
-// "long" slice blocks).  For every group: one epilogue block (nsl = kSlices)
-// in `grp`, and kSlices slice blocks in `sl` whose entries are stored
-// group-major, then slice-major, then row-major starting at entry position
-// nz0.  Row pointers of slice blocks go to brp (positions from brp_base);
+// r's entries in column slice s.  Rows are grouped (at most kSliceRows rows)
+// so that every slice of a group holds at most NB entries (a row with more
+// gets a group of its own and "long" slice blocks).  Each group has kSlices
+// slice blocks in `sl` whose entries are stored group-major, then
+// slice-major, then row-major starting at entry position nz0.  `grp` gets
+// epilogue blocks (nsl = kSlices, kMaxRows rows each) that add up the
+// slice partial sums.  Row pointers of slice blocks go to brp (positions from brp_base);
 // dst[r * kSlices + s] receives the first position of row r's slice s.
 static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int inst, int NB, int64_t nz0,
                          int64_t brp_base, std::vector<Blk>& grp, std::vector<Blk>& sl,
@@ -147,7 +149,7 @@ static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int in
   };
   for (int64_t r = 0; r < nrows; ++r) {
     const int32_t* c = cnt + r * kSlices;
-    bool big = false, over = (r - start) >= kMaxRows;
+    bool big = false, over = (r - start) >= kSliceRows;
     for (int q = 0; q < kSlices; ++q) {
       big |= c[q] > NB;
       over |= acc[q] + c[q] > NB;
@@ -165,18 +167,26 @@ static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int in
   if (groups.empty()) groups.emplace_back(0, 0);
   dst.assign(nrows * kSlices, 0);
   int64_t pos = nz0;
+  // epilogue blocks: kMaxRows consecutive rows each, independent of the groups
+  for (int64_t a = 0; a < std::max<int64_t>(nrows, 1); a += kMaxRows) {
+    Blk ep;
+    ep.r0 = (int32_t)(base + a);
+    ep.r1 = (int32_t)(base + std::min<int64_t>(a + kMaxRows, nrows));
+    ep.inst = inst;
+    ep.meta = blk_meta(BK_STREAM, kSlices, 0);
+    ep.gid = (int32_t)grp.size();
+    ep.rp_off = 0;
+    ep.p0 = 0;
+    ep.pn = 0;
+    grp.push_back(ep);
+  }
   for (size_t g = 0; g < groups.size(); ++g) {
     const int64_t a = groups[g].first, e = groups[g].second;
     Blk ep;
     ep.r0 = (int32_t)(base + a);
     ep.r1 = (int32_t)(base + e);
     ep.inst = inst;
-    ep.meta = blk_meta(BK_STREAM, kSlices, 0);
     ep.gid = (int32_t)g;
-    ep.rp_off = 0;
-    ep.p0 = 0;
-    ep.pn = 0;
-    grp.push_back(ep);
     for (int q = 0; q < kSlices; ++q) {
       Blk k = ep;
       k.rp_off = (int32_t)(brp_base + (int64_t)brp.size());
@@ -937,7 +947,7 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
 // (slices over its constraints) into the column-sliced layout.
 template <class T>
 void Engine<T>::slice_matrix(int id, bool dual) {
-  constexpr int NB = Tile<T>::NB;
+  constexpr int NB = kSliceNB;
   Slot& S = slots_[id];
   const int64_t nrows = dual ? S.m : S.n;
   const int64_t r0 = dual ? S.row0 : S.col0;
@@ -1029,6 +1039,7 @@ void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_
         s.phase = PH_NORMAL;
         s.kbase = g_next_;
         s.tbase = g_next_;
+        s.next_check = g_next_ + s.C;
       }
     }
     slots_[ids[k]].watched = true;
@@ -1191,6 +1202,7 @@ void Engine<T>::run(double time_limit_s) {
   }
   int64_t j = 0;
   bool limit_set = false;
+  double next_print = (double)opt_.verbose;
   while (true) {
     launch_chunk();
     HIPCHECK(hipMemcpyAsync(h_status[j & 1], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost, stream_));
@@ -1200,6 +1212,29 @@ void Engine<T>::run(double time_limit_s) {
       if (all_done(h_status[(j - 1) & 1])) break;
     }
     ++j;
+    if (opt_.verbose > 0) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el >= next_print) {
+        next_print = el + (double)opt_.verbose;
+        int first = -1, running = 0, watched = 0;
+        for (int s = 0; s < nslots_; ++s) {
+          if (!slots_[s].used || !slots_[s].watched) continue;
+          ++watched;
+          if (h_status[(j - 1) & 1][s] == ST_RUNNING) {
+            ++running;
+            if (first < 0) first = s;
+          }
+        }
+        if (first >= 0) {
+          InstState st;
+          HIPCHECK(hipMemcpy(&st, d_st + first, sizeof(InstState), hipMemcpyDeviceToHost));
+          fprintf(stderr, "[halp] %.1fs step %lld: %d/%d LPs running; LP %d: iters %lld restarts %lld kkt %.3e "
+                  "(p %.2e d %.2e gap %.2e) omega %.3e\n", el, (long long)g_next_, running, watched, first,
+                  (long long)st.iters, (long long)st.nrest, st.kkt, st.rel_p, st.rel_d, st.rel_gap, st.omega);
+          fflush(stderr);
+        }
+      }
+    }
     if (!limit_set && time_limit_s >= 0.0) {
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (el > time_limit_s) {

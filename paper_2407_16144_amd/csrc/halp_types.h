@@ -16,8 +16,14 @@ constexpr int kMaxRows = 256;        // rows per "stream" block (one epilogue ro
 constexpr int kNS = 8;               // partial-sum slots per block
 constexpr int kNAcc = 12;            // sums kept from a check step for the following eval step
 
-// nnz per stream block; rows longer than this get a block of their own.
-template <class T> struct Tile { static constexpr int NB = 2048; };
+// Entries per stream block: plain blocks (whole rows) and the slice blocks of
+// column-sliced matrices (measured on MI355X: random gathers, not HBM
+// bandwidth, bound these products, and smaller tiles keep more independent
+// gathers in flight).  Rows longer than a tile get a block of their own.
+constexpr int kPlainNB = 1024;
+constexpr int kSliceNB = 512;
+constexpr int kSliceRows = 128;  // rows per sliced row group
+template <class T> struct Tile { static constexpr int NB = kPlainNB; };
 
 enum Mode : int { M_SKIP = 0, M_NORMAL = 1, M_CHECK = 2, M_EVAL = 3, M_RESID = 4 };
 enum Phase : int { PH_NORMAL = 0, PH_EVAL = 1, PH_RESID = 2 };
@@ -65,6 +71,7 @@ struct alignas(16) InstState {
   // dynamic state
   int32_t status, phase;
   int64_t kbase, tbase, nrest, checks;
+  int64_t next_check;                // global step index of the next check step
   double omega, tau, sigma, r0;
   double acc[kNAcc];
   // last check

@@ -103,21 +103,34 @@ __device__ __forceinline__ void lds_barrier() {
 // Result: s_rsum[a][r - b.r0].
 // ---------------------------------------------------------------------------
 
-template <class T>
+template <class T, int NB = kPlainNB>
 struct TileRegs {
-  static constexpr int EPT = Tile<T>::NB / kThreads;
+  static constexpr int EPT = NB / kThreads;
   int cidx[EPT];
   T v[EPT];
+  T p[EPT];  // products with a gathered vector
 };
+
+// Products with the step's usual gathered vector, issued before the LP
+// state is read (the state only decides whether they are used).
+template <class T, int NB>
+__device__ __forceinline__ void spec_products(const Blk& b, const T* __restrict__ src, TileRegs<T, NB>& R) {
+  if (blk_kind(b) != BK_STREAM) return;
+#pragma unroll
+  for (int k = 0; k < TileRegs<T, NB>::EPT; ++k) {
+    const int e = (int)threadIdx.x + k * kThreads;
+    if (e < b.pn) R.p[k] = R.v[k] * src[R.cidx[k]];
+  }
+}
 
 // Loads a stream block's entries (coalesced) into registers; independent of
 // the step mode, so callers issue it before reading the LP state.
-template <class T>
+template <class T, int NB>
 __device__ __forceinline__ void load_tile(const Blk& b, const int32_t* __restrict__ ci,
-                                          const T* __restrict__ val, TileRegs<T>& R) {
+                                          const T* __restrict__ val, TileRegs<T, NB>& R) {
   if (blk_kind(b) != BK_STREAM) return;
 #pragma unroll
-  for (int k = 0; k < TileRegs<T>::EPT; ++k) {
+  for (int k = 0; k < TileRegs<T, NB>::EPT; ++k) {
     const int e = (int)threadIdx.x + k * kThreads;
     if (e < b.pn) {
       R.cidx[k] = ci[b.p0 + e];
@@ -126,83 +139,72 @@ __device__ __forceinline__ void load_tile(const Blk& b, const int32_t* __restric
   }
 }
 
-template <class T, int NV>
-__device__ void block_spmv_regs(const Blk& b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                const T* __restrict__ val, const TileRegs<T>& R, const T* __restrict__ s0,
-                                const T* __restrict__ s1, const T* __restrict__ s2, T* s_prod,
-                                T (*s_rsum)[kMaxRows], int* s_rp, double (*s_red)[kNS], T scale0 = (T)1) {
+// One gathered vector: row sums into out[r - b.r0] (LDS).
+template <class T, int NB>
+__device__ void block_spmv1(const Blk& b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const T* __restrict__ val, const TileRegs<T, NB>& R, const T* __restrict__ src,
+                            T* s_prod, T* out, int* s_rp, double (*s_red)[kNS], T scale = (T)1,
+                            bool have_products = false) {
   const int tid = threadIdx.x;
   const int nrows = b.r1 - b.r0;
   const int p0 = b.p0, pn = b.pn;
   if (blk_kind(b) == BK_LONG) {
-    T acc[NV][4];
-#pragma unroll
-    for (int a = 0; a < NV; ++a)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[a][u] = (T)0;
+    T acc0 = (T)0, acc1 = (T)0;
     int e = tid;
-    for (; e + 3 * kThreads < pn; e += 4 * kThreads) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int c = ci[p0 + e + u * kThreads];
-        const T v = val[p0 + e + u * kThreads];
-        acc[0][u] += v * s0[c];
-        if constexpr (NV > 1) acc[1][u] += v * s1[c];
-        if constexpr (NV > 2) acc[2][u] += v * s2[c];
-      }
+    for (; e + kThreads < pn; e += 2 * kThreads) {
+      const int c0 = ci[p0 + e], c1 = ci[p0 + e + kThreads];
+      const T v0 = val[p0 + e], v1 = val[p0 + e + kThreads];
+      acc0 += v0 * src[c0];
+      acc1 += v1 * src[c1];
     }
-    for (; e < pn; e += kThreads) {
-      const int c = ci[p0 + e];
-      const T v = val[p0 + e];
-      acc[0][0] += v * s0[c];
-      if constexpr (NV > 1) acc[1][0] += v * s1[c];
-      if constexpr (NV > 2) acc[2][0] += v * s2[c];
-    }
-#pragma unroll
-    for (int a = 0; a < NV; ++a) {
-      T t = (acc[a][0] + acc[a][1]) + (acc[a][2] + acc[a][3]);
-      t = wave_sum(t);
-      if ((tid & 63) == 0) s_red[tid >> 6][a] = (double)t;
-    }
+    if (e < pn) acc0 += val[p0 + e] * src[ci[p0 + e]];
+    T t = wave_sum(acc0 + acc1);
+    if ((tid & 63) == 0) s_red[tid >> 6][0] = (double)t;
     lds_barrier();
     if (tid == 0) {
+      T u = (T)s_red[0][0];
 #pragma unroll
-      for (int a = 0; a < NV; ++a) {
-        T t = (T)s_red[0][a];
-#pragma unroll
-        for (int w = 1; w < kThreads / 64; ++w) t += (T)s_red[w][a];
-        s_rsum[a][0] = (a == 0) ? t * scale0 : t;
-      }
+      for (int w = 1; w < kThreads / 64; ++w) u += (T)s_red[w][0];
+      out[0] = u * scale;
     }
     lds_barrier();
     return;
   }
-  constexpr int EPT = TileRegs<T>::EPT;
+  constexpr int EPT = TileRegs<T, NB>::EPT;
   for (int i = tid; i <= nrows; i += kThreads) s_rp[i] = rp[i] - p0;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = tid + k * kThreads;
+    if (e < pn) s_prod[e] = have_products ? R.p[k] : R.v[k] * src[R.cidx[k]];
+  }
+  lds_barrier();
   const int G = group_size(nrows);
   const int lane = tid & (G - 1);
   const int rpb = kThreads / G;  // rows per pass
-#pragma unroll
-  for (int a = 0; a < NV; ++a) {
-    const T* __restrict__ src = (a == 0) ? s0 : (a == 1) ? s1 : s2;
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-      const int e = tid + k * kThreads;
-      if (e < pn) s_prod[e] = R.v[k] * src[R.cidx[k]];
+  for (int base = 0; base < nrows; base += rpb) {
+    const int r = base + tid / G;
+    T acc = (T)0;
+    if (r < nrows) {
+      const int q1 = s_rp[r + 1];
+      for (int q = s_rp[r] + lane; q < q1; q += G) acc += s_prod[q];
     }
-    lds_barrier();
-    for (int base = 0; base < nrows; base += rpb) {
-      const int r = base + tid / G;
-      T acc = (T)0;
-      if (r < nrows) {
-        const int q1 = s_rp[r + 1];
-        for (int q = s_rp[r] + lane; q < q1; q += G) acc += s_prod[q];
-      }
-      for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      if (lane == 0 && r < nrows) s_rsum[a][r] = (a == 0) ? acc * scale0 : acc;
-    }
-    lds_barrier();
+    for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0 && r < nrows) out[r] = acc * scale;
   }
+  lds_barrier();
+}
+
+// NV gathered vectors, one after the other over the same register tile
+template <class T, int NV, int NB>
+__device__ __forceinline__ void block_spmv_regs(const Blk& b, const int32_t* __restrict__ rp,
+                                                const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                const TileRegs<T, NB>& R, const T* __restrict__ s0,
+                                                const T* __restrict__ s1, const T* __restrict__ s2, T* s_prod,
+                                                T (*s_rsum)[kMaxRows], int* s_rp, double (*s_red)[kNS],
+                                                T scale0 = (T)1) {
+  block_spmv1<T, NB>(b, rp, ci, val, R, s0, s_prod, s_rsum[0], s_rp, s_red, scale0);
+  if constexpr (NV > 1) block_spmv1<T, NB>(b, rp, ci, val, R, s1, s_prod, s_rsum[1], s_rp, s_red);
+  if constexpr (NV > 2) block_spmv1<T, NB>(b, rp, ci, val, R, s2, s_prod, s_rsum[2], s_rp, s_red);
 }
 
 template <class T, int NV>
@@ -211,9 +213,9 @@ __device__ __forceinline__ void block_spmv(const Blk& b, const int32_t* __restri
                                            const T* __restrict__ s0, const T* __restrict__ s1,
                                            const T* __restrict__ s2, T* s_prod, T (*s_rsum)[kMaxRows],
                                            int* s_rp, double (*s_red)[kNS], T scale0 = (T)1) {
-  TileRegs<T> R;
-  load_tile<T>(b, ci, val, R);
-  block_spmv_regs<T, NV>(b, rp, ci, val, R, s0, s1, s2, s_prod, s_rsum, s_rp, s_red, scale0);
+  TileRegs<T, kPlainNB> R;
+  load_tile<T, kPlainNB>(b, ci, val, R);
+  block_spmv_regs<T, NV, kPlainNB>(b, rp, ci, val, R, s0, s1, s2, s_prod, s_rsum, s_rp, s_red, scale0);
 }
 
 // Row sums of a sliced row group: the kSlices partial sums written by the
@@ -238,13 +240,15 @@ __device__ __forceinline__ void gather_slices(const Blk& b, const T* __restrict_
 // step modes
 // ---------------------------------------------------------------------------
 
+// Mode of step g for one LP.  Checks fall at inner counters k = C, 2C, ...
+// of an epoch (k = g - kbase); the controller keeps the step index of the
+// next one in next_check.
 __device__ __forceinline__ int step_mode(const InstState& S, int64_t g) {
   if (S.status != ST_RUNNING) return M_SKIP;
   if (S.phase == PH_EVAL) return M_EVAL;
   if (S.phase == PH_RESID) return M_RESID;
-  const int64_t k = g - S.kbase;
-  if (k < 0) return M_SKIP;
-  if (k > 0 && (k % S.C) == 0) return M_CHECK;
+  if (g < S.kbase) return M_SKIP;
+  if (g == S.next_check) return M_CHECK;
   return M_NORMAL;
 }
 
@@ -278,8 +282,9 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
   const int64_t j = (int64_t)b.r0 + (own ? t : 0);
   // entries and epilogue operands are loaded before the LP state is read,
   // so their latency overlaps the state loads (none depends on the mode)
-  TileRegs<T> R;
-  load_tile<T>(b, A.KT_ci, A.KT_v, R);
+  TileRegs<T, kPlainNB> R;
+  load_tile<T, kPlainNB>(b, A.KT_ci, A.KT_v, R);
+  spec_products<T, kPlainNB>(b, A.y, R);
   T cj = 0, lj = 0, uj = 0, xo = 0, x0j = 0, kty = 0;
   if (own) {
     cj = A.c[j];
@@ -302,10 +307,11 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartP, A.NS, s_rsum);
     else if (!resid) gather_slices<T, 1>(b, A.spartP, A.NS, s_rsum);
   } else if (mode == M_EVAL) {
-    block_spmv_regs<T, 3>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp,
+    block_spmv_regs<T, 3, kPlainNB>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp,
                           s_red);
   } else if (!resid) {
-    block_spmv_regs<T, 1>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.y, A.y, A.y, s_prod, s_rsum, s_rp, s_red);
+    block_spmv1<T, kPlainNB>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.y, s_prod, s_rsum[0], s_rp, s_red, (T)1,
+                             true);
   }
 
   double ps[kNS];
@@ -377,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
 // gathering y (or yT, cy1, cy2).
 template <class T>
 __global__ __launch_bounds__(kThreads) void slice_step(IterArgs<T> A, int step, int dual) {
-  __shared__ T s_prod[Tile<T>::NB];
+  __shared__ T s_prod[kSliceNB];
   __shared__ T s_rsum[3][kMaxRows];
   __shared__ int s_rp[kMaxRows + 1];
   __shared__ double s_red[kThreads / 64][kNS];
@@ -386,8 +392,10 @@ __global__ __launch_bounds__(kThreads) void slice_step(IterArgs<T> A, int step, 
   const int32_t* rp = (dual ? A.brpK : A.brpKT) + b.rp_off;
   const int32_t* ci = dual ? A.K_ci : A.KT_ci;
   const T* val = dual ? A.K_v : A.KT_v;
-  TileRegs<T> R;
-  load_tile<T>(b, ci, val, R);
+  TileRegs<T, kSliceNB> R;
+  load_tile<T, kSliceNB>(b, ci, val, R);
+  const T* src = dual ? A.xbar : A.y;
+  spec_products<T, kSliceNB>(b, src, R);
   const InstState& S = A.st[b.inst];
   const int64_t g = *A.gbase + step;
   const int mode = step_mode(S, g);
@@ -396,11 +404,10 @@ __global__ __launch_bounds__(kThreads) void slice_step(IterArgs<T> A, int step, 
   const int64_t space = dual ? A.MS : A.NS;
   const int nv = mode == M_EVAL ? 3 : 1;
   if (mode == M_EVAL) {
-    if (dual) block_spmv_regs<T, 3>(b, rp, ci, val, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
-    else block_spmv_regs<T, 3>(b, rp, ci, val, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+    if (dual) block_spmv_regs<T, 3, kSliceNB>(b, rp, ci, val, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    else block_spmv_regs<T, 3, kSliceNB>(b, rp, ci, val, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
   } else {
-    const T* src = dual ? A.xbar : A.y;
-    block_spmv_regs<T, 1>(b, rp, ci, val, R, src, src, src, s_prod, s_rsum, s_rp, s_red);
+    block_spmv1<T, kSliceNB>(b, rp, ci, val, R, src, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
   }
   const int nrows = b.r1 - b.r0;
   const int sl = blk_slice(b);
@@ -497,9 +504,11 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
     S.nrest += 1;
     S.phase = PH_RESID;
     S.kbase = g + 1;
+    S.next_check = g + 1 + S.C;
   } else {
     S.phase = PH_NORMAL;
     S.kbase += 1;
+    S.next_check = g + S.C;
   }
 }
 
@@ -523,8 +532,9 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
   const bool own = t < nrows;
   const int64_t i = (int64_t)b.r0 + (own ? t : 0);
   // entries and epilogue operands are loaded before the LP state is read
-  TileRegs<T> R;
-  load_tile<T>(b, A.K_ci, A.K_v, R);
+  TileRegs<T, kPlainNB> R;
+  load_tile<T, kPlainNB>(b, A.K_ci, A.K_v, R);
+  spec_products<T, kPlainNB>(b, A.xbar, R);
   T qi = 0, yo = 0, y0i = 0, kxpi = 0;
   if (own) {
     qi = A.q[i];
@@ -545,10 +555,9 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartD, A.MS, s_rsum);
     else gather_slices<T, 1>(b, A.spartD, A.MS, s_rsum);
   } else if (mode == M_EVAL) {
-    block_spmv_regs<T, 3>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    block_spmv_regs<T, 3, kPlainNB>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
   } else {
-    block_spmv_regs<T, 1>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xbar, A.xbar, A.xbar, s_prod, s_rsum, s_rp,
-                          s_red);
+    block_spmv1<T, kPlainNB>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xbar, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
   }
 
   double ps[kNS];
