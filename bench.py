@@ -92,15 +92,20 @@ def run_batch(args):
     import torch
     import lpgen
     import paper_2407_16144_amd as halp
+    t0 = time.perf_counter()
     lps = lpgen.batch(count=args.batch_count)
     nnz = sum(lp.nnz for lp in lps)
+    print(f"generated {len(lps)} LPs ({nnz} nnz) in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+          flush=True)
     arr, keep = halp.make_problems(lps, on_device=True)
     torch.cuda.synchronize()
-    opt = _opts(halp, args, profile=args.profile_every)
+    opt = _opts(halp, args, profile=args.profile_every, verbose=args.verbose)
     stream = torch.cuda.current_stream().cuda_stream
 
     def step():
+        c0 = time.perf_counter()
         h = halp.lp_batch_create_from(arr, len(lps), True, stream=stream, opt=opt)
+        print(f"batch created in {time.perf_counter() - c0:.2f}s", file=sys.stderr, flush=True)
         try:
             halp.lp_batch_solve(h, args.tol, args.max_iter, args.time_limit)
             res = [halp.lp_batch_status(h, i).as_dict() for i in range(len(lps))]
@@ -222,8 +227,8 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--method", default="r2hpdhg", choices=["rhpdhg", "r2hpdhg"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tol", type=float, default=1e-4)

@@ -229,10 +229,15 @@ def scaled_powerlaw(seed: int, m: int, n: int, nnz_per_col: float = 8.0) -> LP:
 # infeasible / unbounded variants (certificates known in closed form)
 # --------------------------------------------------------------------------
 
-def add_contradictory_rows(lp: LP, seed: int, k: int = 8, gap: float = 1.0) -> LP:
+def add_contradictory_rows(lp: LP, seed: int, k: int = 8, gap: float = 1.0,
+                           rel_gap: float | None = None) -> LP:
     """Append two equality rows g^T x = beta and g^T x = beta + gap (g with k
     nonzeros) at the end of the equality block: primal infeasible, with the
-    Farkas ray y = (-1, +1) on those two rows."""
+    Farkas ray y = (-1, +1) on those two rows.  With rel_gap the gap is
+    rel_gap * (1 + ||rhs||), so that the infeasibility stays visible to a
+    relative KKT test on badly scaled instances."""
+    if rel_gap is not None:
+        gap = rel_gap * (1.0 + float(np.linalg.norm(lp.rhs)))
     rng = np.random.default_rng(seed)
     n = lp.n
     gcols = np.sort(rng.choice(n, size=min(k, n), replace=False)).astype(np.int32)
@@ -356,7 +361,7 @@ def batch_sizes(seed: int, count: int = 512, m_lo: int = 500, m_hi: int = 20000)
 def batch_instance(seed: int, m: int, n: int, infeasible: bool) -> LP:
     lp = scaled_powerlaw(seed, int(m), int(n))
     if infeasible:
-        lp = add_contradictory_rows(lp, seed + 7_000_000)
+        lp = add_contradictory_rows(lp, seed + 7_000_000, rel_gap=0.1)
     return lp
 
 
@@ -407,7 +412,7 @@ def request_instance(r: Request) -> LP:
         return scaled_powerlaw(r.seed, r.m, r.n, nnz_per_col=10.0)
     lp = scaled_powerlaw(r.seed, r.m, r.n)
     if r.kind == "infeasible":
-        lp = add_contradictory_rows(lp, r.seed + 7)
+        lp = add_contradictory_rows(lp, r.seed + 7, rel_gap=0.1)
     elif r.kind == "unbounded":
         lp = add_unbounded_column(lp, r.seed + 7)
     return lp

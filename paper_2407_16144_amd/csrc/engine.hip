@@ -274,6 +274,9 @@ class Engine final : public EngineBase {
   void allocate();
   void release_all();
   void rebuild_schedules();
+  int scheduled_ = 0;          // LPs in the current schedules
+  bool compacted_ = false;     // current schedules leave finished LPs out
+  const int* finished_ = nullptr;  // status words used to leave finished LPs out (compaction)
   void launch_chunk();
   void collect_times();
   void transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1, const std::vector<Blk>& bD);
@@ -772,6 +775,7 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
     r.w = (int)nD.size();
     nr.push_back(r);
   }
+  compacted_ = false;
   preprocess(ids, nP, nD, nr);
   // column-slice the matrices whose gathered vector would not stay in one L2
   for (int id : ids) {
@@ -1073,6 +1077,7 @@ void Engine<T>::rebuild_schedules() {
   for (int s = 0; s < nslots_; ++s) {
     const Slot& sl = slots_[s];
     if (!sl.used) continue;
+    if (finished_ && finished_[s] != ST_RUNNING) continue;  // done: its blocks would only exit
     int4 r;
     r.x = (int)P.size();
     append(PS, sl.bPS, r.x);
@@ -1097,6 +1102,7 @@ void Engine<T>::rebuild_schedules() {
     n = (int64_t)v.size();
     if (n) HIPCHECK(hipMemcpyAsync(d, v.data(), sizeof(Blk) * n, hipMemcpyHostToDevice, stream_));
   };
+  scheduled_ = (int)live.size();
   upload(P, d_schedP, capP_, nP_, &partP);
   upload(D, d_schedD, capD_, nD_, &partD);
   upload(PS, d_schedPS, capPS_, nPS_, nullptr);
@@ -1127,7 +1133,7 @@ void Engine<T>::rebuild_schedules() {
 
 template <class T>
 void Engine<T>::launch_chunk() {
-  if (sched_dirty_) rebuild_schedules();
+  if (sched_dirty_ && !compacted_) rebuild_schedules();
   if (nP_ == 0 || nD_ == 0) return;
   const IterArgs<T> A = args();
   const int CH = opt_.chunk;
@@ -1189,7 +1195,10 @@ void Engine<T>::collect_times() {
 template <class T>
 void Engine<T>::run(double time_limit_s) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (sched_dirty_) rebuild_schedules();
+  if (sched_dirty_) {
+    compacted_ = false;
+    rebuild_schedules();
+  }
   auto all_done = [&](const int* h) {
     for (int s = 0; s < nslots_; ++s)
       if (slots_[s].used && slots_[s].watched && h[s] == ST_RUNNING) return false;
@@ -1210,6 +1219,19 @@ void Engine<T>::run(double time_limit_s) {
     if (j >= 1) {
       HIPCHECK(hipEventSynchronize(ev_[(j - 1) & 1]));
       if (all_done(h_status[(j - 1) & 1])) break;
+      // leave finished LPs out of the schedules once half of them are done
+      int running = 0;
+      for (int s = 0; s < nslots_; ++s) running += slots_[s].used && h_status[(j - 1) & 1][s] == ST_RUNNING;
+      if (scheduled_ > 1 && 2 * running <= scheduled_) {
+        HIPCHECK(hipStreamSynchronize(stream_));
+        HIPCHECK(hipMemcpy(h_status[0], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost));
+        std::memcpy(h_status[1], h_status[0], sizeof(int) * nslots_);
+        finished_ = h_status[0];
+        rebuild_schedules();
+        finished_ = nullptr;
+        sched_dirty_ = true;  // the next add / remove / solve rebuilds the full schedules
+        compacted_ = true;
+      }
     }
     ++j;
     if (opt_.verbose > 0) {
@@ -1279,8 +1301,8 @@ void Engine<T>::remove(const std::vector<int>& ids) {
     S = Slot();
     h_status[0][id] = h_status[1][id] = 0;
   }
-  // parked slots never run: mark them finished on the device
   sched_dirty_ = true;
+  compacted_ = false;
 }
 
 template <class T>
