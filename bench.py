@@ -35,6 +35,38 @@ def algorithmic_bytes(n, m, nnz, s):
     return primal, dual
 
 
+def kernel_bytes(n, m, nnz, s, primal_sliced, dual_sliced):
+    """Algorithmic bytes per launch of each of the four kernels of a plain
+    step.  Where a product is column-sliced, its slice kernel is charged the
+    matrix, row pointers and gathered vector, and the step kernel only its
+    epilogue; the slice partial sums exchanged between the two are not
+    algorithmic traffic and are charged to neither."""
+    pmat = nnz * (s + 4) + 4 * (n + 1) + s * m
+    dmat = nnz * (s + 4) + 4 * (m + 1) + s * n
+    pepi, depi = 7 * s * n, 4 * s * m
+    return {"primal_slice": pmat if primal_sliced else 0,
+            "primal_step": pepi + (0 if primal_sliced else pmat),
+            "dual_slice": dmat if dual_sliced else 0,
+            "dual_step": depi + (0 if dual_sliced else dmat)}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (profiles/traffic_<workload>.json: FETCH_SIZE and
+    WRITE_SIZE runs scaled by a streaming-kernel calibration), or None when
+    there is none or the kernel sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2407_16144_amd import rocprof_summary
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != rocprof_summary.kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else int(round(k["traffic_bytes"]))
+
+
 def cpu_baseline(lp, eta, gpu_iters, gpu_power_iters, method, budget_s=30.0):
     """Oracle timed on a bounded sample of the same LP (single process):
     scaling + one epoch of 65 iterations with the GPU's step size, and ten
@@ -125,7 +157,8 @@ def run_batch(args):
         s0 = time.perf_counter()
         res, kt = step()
         lat.append(time.perf_counter() - s0)
-        kp, kd, kn = kp + kt[0], kd + kt[1], kn + kt[2]
+        kp, kd, kn = (kp + kt["primal_slice_ms"] + kt["primal_ms"],
+                      kd + kt["dual_slice_ms"] + kt["dual_ms"], kn + kt["steps"])
         st = [r["status"] for r in res]
         print(f"batch step {i}: {lat[-1]:.2f}s optimal={st.count(1)} infeasible={st.count(2)} "
               f"limit={st.count(4)}", file=sys.stderr, flush=True)
@@ -245,7 +278,9 @@ def main():
     ap.add_argument("--verbose", type=int, default=20, help="library progress line every N seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
-                    help="also run a plain device copy of this many MB (counter calibration)")
+                    help="first run a plain streaming kernel (y = -x, FP64) over this many MB "
+                         "(calibration of the HBM byte counters)")
+    ap.add_argument("--no-graph", action="store_true", help="launch steps without hipGraphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})",
@@ -267,9 +302,10 @@ def main():
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        print(f"copy probe: {nel * 8} bytes read and written per launch", file=sys.stderr, flush=True)
+        print(f"copy probe: neg kernel reads and writes {nel * 8} bytes per launch", file=sys.stderr,
+              flush=True)
     lp = {"large": lpgen.large_single, "mixed": lpgen.large_mixed, "tiny": lpgen.tiny}[args.workload]()
     dev = torch.device("cuda", 0)
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
@@ -280,7 +316,7 @@ def main():
     opt = halp.lp_default_options(
         method=halp.LP_METHOD_R2HPDHG if args.method == "r2hpdhg" else halp.LP_METHOD_RHPDHG,
         precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64,
-        profile=args.profile_every, verbose=args.verbose)
+        profile=args.profile_every, verbose=args.verbose, use_graph=0 if args.no_graph else 1)
 
     def step():
         h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,
@@ -299,8 +335,7 @@ def main():
               f"kkt={r['rel_kkt']:.2e} t={r['seconds']:.2f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     lat, results = [], []
-    kp = kd = 0.0
-    kn = 0
+    ksum = {"primal_slice_ms": 0.0, "primal_ms": 0.0, "dual_slice_ms": 0.0, "dual_ms": 0.0, "steps": 0}
     t0 = time.perf_counter()
     for i in range(args.steps):
         s0 = time.perf_counter()
@@ -308,9 +343,8 @@ def main():
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - s0)
         results.append(r)
-        kp += kt[0]
-        kd += kt[1]
-        kn += kt[2]
+        for k in ksum:
+            ksum[k] += kt[k]
         print(f"step {i}: status={halp.STATUS_NAMES[r['status']]} iters={r['iters']} "
               f"kkt={r['rel_kkt']:.2e} t={lat[-1]:.2f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -319,16 +353,27 @@ def main():
     value = solved / wall
     iters = results[-1]["iters"]
     s = 8 if args.precision == "fp64" else 4
-    bp, bd = algorithmic_bytes(lp.n, lp.m, lp.nnz, s)
-    tp, td = kp / max(kn, 1), kd / max(kn, 1)
-    dom = ("dual_step", bd, td) if td >= tp else ("primal_step", bp, tp)
-    achieved = dom[1] / (dom[2] * 1e-3) / 1e9 if dom[2] > 0 else 0.0
+    kn = max(ksum["steps"], 1)
+    avg = {k: ksum[k + "_ms"] / kn for k in ("primal_slice", "primal", "dual_slice", "dual")}
+    # a slice kernel that launched nothing times as a pair of adjacent events
+    primal_sliced, dual_sliced = avg["primal_slice"] > 2e-3, avg["dual_slice"] > 2e-3
+    kb = kernel_bytes(lp.n, lp.m, lp.nnz, s, primal_sliced, dual_sliced)
+    names = {"primal_slice": "primal_slice_step", "primal": "primal_step",
+             "dual_slice": "dual_slice_step", "dual": "dual_step"}
+    byname = {"primal_slice": kb["primal_slice"], "primal": kb["primal_step"],
+              "dual_slice": kb["dual_slice"], "dual": kb["dual_step"]}
+    dom = max(avg, key=lambda k: avg[k])
+    achieved = byname[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
+    tstep = sum(avg.values())
+    wl_key = f"{args.workload}-{args.precision}"
+    tr = measured_traffic(wl_key, names[dom] + ("<double>" if s == 8 else "<float>"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dom[0], "bytes_per_launch": int(dom[1]),
-                "avg_ms": {"primal_step": round(tp, 5), "dual_step": round(td, 5)},
-                "timed_steps": kn,
-                "step_achieved_GBs": round((bp + bd) / ((tp + td) * 1e-3) / 1e9, 1) if tp + td > 0 else 0}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+                "kernel": names[dom], "bytes_per_launch": int(byname[dom]),
+                "avg_ms": {names[k]: round(v, 5) for k, v in avg.items()},
+                "bytes": {names[k]: int(v) for k, v in byname.items()},
+                "timed_steps": ksum["steps"],
+                "step_achieved_GBs": round(sum(byname.values()) / (tstep * 1e-3) / 1e9, 1) if tstep > 0 else 0}
     lat_sorted = sorted(lat)
     p50 = lat_sorted[len(lat) // 2]
     p99 = lat_sorted[min(len(lat) - 1, math.ceil(0.99 * len(lat)) - 1)]

@@ -159,9 +159,22 @@ int lp_get_solution(const lp_solver* s, double* x, double* y, int to_device);
  * otherwise. */
 int lp_get_certificate(const lp_solver* s, double* ray, int to_device);
 
-/* Summed durations (ms) of the primal-step and dual-step kernels over the
- * steps timed with HIP events (options.profile > 0), and that step count. */
-int lp_kernel_times(const lp_solver* s, double* primal_ms, double* dual_ms, int64_t* steps);
+/* Durations (ms) of the four kernels of a step, summed over the steps timed
+ * with HIP events on the solver's stream (options.profile > 0: every
+ * profile-th chunk of steps is launched without a graph and timed).  The
+ * slice kernels compute the per-XCD column-slice partial products of a
+ * column-sliced K^T (primal) or K (dual); where no row group is sliced they
+ * launch nothing and their sums stay at (event overhead) ~0. */
+typedef struct {
+  double primal_slice_ms;
+  double primal_ms;          /* primal_step: K^T y and the x half of eq. (pdhg) + Halpern blend */
+  double dual_slice_ms;
+  double dual_ms;            /* dual_step: K(2x+ - x), the y half of eq. (pdhg), controller */
+  int64_t steps;             /* number of timed steps */
+} lp_kernel_timing;
+
+/* Fills *out.  LP_ERR_INVALID for a NULL argument. */
+int lp_kernel_times(const lp_solver* s, lp_kernel_timing* out);
 
 void lp_destroy(lp_solver* s);
 
@@ -197,7 +210,7 @@ int lp_batch_solve(lp_batch* b, double rel_kkt_tol, int64_t max_iter, double tim
 int lp_batch_status(const lp_batch* b, int index, lp_result* out);
 int lp_batch_get_solution(const lp_batch* b, int index, double* x, double* y, int to_device);
 int lp_batch_get_certificate(const lp_batch* b, int index, double* ray, int to_device);
-int lp_batch_kernel_times(const lp_batch* b, double* primal_ms, double* dual_ms, int64_t* steps);
+int lp_batch_kernel_times(const lp_batch* b, lp_kernel_timing* out);
 void lp_batch_destroy(lp_batch* b);
 
 /* ---------------------------------------------------------------- serving */

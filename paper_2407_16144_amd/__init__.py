@@ -58,6 +58,14 @@ class lp_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class lp_kernel_timing(C.Structure):
+    _fields_ = [("primal_slice_ms", C.c_double), ("primal_ms", C.c_double),
+                ("dual_slice_ms", C.c_double), ("dual_ms", C.c_double), ("steps", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class lp_problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("m_eq", C.c_int64), ("m_ineq", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
@@ -74,14 +82,14 @@ _sig = {
     "lp_status": (C.c_int, [_P, _P]),
     "lp_get_solution": (C.c_int, [_P, _P, _P, C.c_int]),
     "lp_get_certificate": (C.c_int, [_P, _P, C.c_int]),
-    "lp_kernel_times": (C.c_int, [_P, _P, _P, _P]),
+    "lp_kernel_times": (C.c_int, [_P, _P]),
     "lp_destroy": (None, [_P]),
     "lp_batch_create": (C.c_int, [_P, C.c_int, _P, C.c_int, _P, _P]),
     "lp_batch_solve": (C.c_int, [_P, C.c_double, C.c_int64, C.c_double]),
     "lp_batch_status": (C.c_int, [_P, C.c_int, _P]),
     "lp_batch_get_solution": (C.c_int, [_P, C.c_int, _P, _P, C.c_int]),
     "lp_batch_get_certificate": (C.c_int, [_P, C.c_int, _P, C.c_int]),
-    "lp_batch_kernel_times": (C.c_int, [_P, _P, _P, _P]),
+    "lp_batch_kernel_times": (C.c_int, [_P, _P]),
     "lp_batch_destroy": (None, [_P]),
     "lp_server_create": (C.c_int, [_P, C.c_int64, C.c_int, _P, _P]),
     "lp_server_submit": (C.c_int, [_P, _P, C.c_double, C.c_int64, C.c_double, _P]),
@@ -197,9 +205,10 @@ def lp_get_certificate(h, length):
 
 
 def lp_kernel_times(h):
-    a, b, n = C.c_double(), C.c_double(), C.c_int64()
-    _check(_lib.lp_kernel_times(h, C.byref(a), C.byref(b), C.byref(n)))
-    return a.value, b.value, n.value
+    """Summed per-kernel durations (ms) of the timed steps, as a dict."""
+    t = lp_kernel_timing()
+    _check(_lib.lp_kernel_times(h, C.byref(t)))
+    return t.as_dict()
 
 
 def lp_destroy(h):
@@ -268,9 +277,9 @@ def lp_batch_get_certificate(h, i, length):
 
 
 def lp_batch_kernel_times(h):
-    a, b, n = C.c_double(), C.c_double(), C.c_int64()
-    _check(_lib.lp_batch_kernel_times(h, C.byref(a), C.byref(b), C.byref(n)))
-    return a.value, b.value, n.value
+    t = lp_kernel_timing()
+    _check(_lib.lp_batch_kernel_times(h, C.byref(t)))
+    return t.as_dict()
 
 
 def lp_batch_destroy(h):

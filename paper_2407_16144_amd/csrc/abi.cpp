@@ -373,13 +373,15 @@ int lp_get_certificate(const lp_solver* s, double* ray, int to_device) {
   });
 }
 
-int lp_kernel_times(const lp_solver* s, double* primal_ms, double* dual_ms, int64_t* steps) {
+int lp_kernel_times(const lp_solver* s, lp_kernel_timing* out) {
   return guarded([&]() -> int {
-    if (!s || !primal_ms || !dual_ms || !steps) return fail(LP_ERR_INVALID, "null argument");
+    if (!s || !out) return fail(LP_ERR_INVALID, "null argument");
     const halp::KernelTimes t = s->eng->kernel_times();
-    *primal_ms = t.primal_ms;
-    *dual_ms = t.dual_ms;
-    *steps = t.launches;
+    out->primal_slice_ms = t.primal_slice_ms;
+    out->primal_ms = t.primal_ms;
+    out->dual_slice_ms = t.dual_slice_ms;
+    out->dual_ms = t.dual_ms;
+    out->steps = t.launches;
     return LP_OK;
   });
 }
@@ -456,13 +458,15 @@ int lp_batch_get_certificate(const lp_batch* b, int index, double* ray, int to_d
   });
 }
 
-int lp_batch_kernel_times(const lp_batch* b, double* primal_ms, double* dual_ms, int64_t* steps) {
+int lp_batch_kernel_times(const lp_batch* b, lp_kernel_timing* out) {
   return guarded([&]() -> int {
-    if (!b || !primal_ms || !dual_ms || !steps) return fail(LP_ERR_INVALID, "null argument");
+    if (!b || !out) return fail(LP_ERR_INVALID, "null argument");
     const halp::KernelTimes t = b->eng->kernel_times();
-    *primal_ms = t.primal_ms;
-    *dual_ms = t.dual_ms;
-    *steps = t.launches;
+    out->primal_slice_ms = t.primal_slice_ms;
+    out->primal_ms = t.primal_ms;
+    out->dual_slice_ms = t.dual_slice_ms;
+    out->dual_ms = t.dual_ms;
+    out->steps = t.launches;
     return LP_OK;
   });
 }

@@ -46,14 +46,16 @@ struct Options {
   int chunk = 64;
   int use_graph = 1;
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
-  int64_t slice_min_bytes = 2 << 20;
-  double polish_tol = 1e-6;  // fp32: solve to this tolerance in fp32, then polish in fp64  // column-slice a matrix whose gathered vector is larger (< 0: never)
+  int64_t slice_min_bytes = 2 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
+  double polish_tol = 1e-6;  // fp32: solve to this tolerance in fp32, then polish in fp64
   int verbose = 0;
 };
 
+// Kernel durations summed over the steps timed with HIP events; a slice
+// kernel runs only where a product is column-sliced (else its sum stays 0).
 struct KernelTimes {
-  double primal_ms = 0.0, dual_ms = 0.0;  // summed over timed launches
-  int64_t launches = 0;                   // timed steps (one primal + one dual launch each)
+  double primal_slice_ms = 0.0, primal_ms = 0.0, dual_slice_ms = 0.0, dual_ms = 0.0;
+  int64_t launches = 0;  // timed steps
 };
 
 struct Result {

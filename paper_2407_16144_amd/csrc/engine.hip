@@ -328,7 +328,8 @@ class Engine final : public EngineBase {
   hipGraph_t graph_ = nullptr;
   std::vector<InstState> h_st_;
   int64_t chunk_count_ = 0;
-  std::vector<hipEvent_t> pev_;  // 3 events per profiled step, read after the solve
+  std::vector<hipEvent_t> pev_;  // 5 events per step of one chunk, reused by each timed chunk
+  bool pev_pending_ = false;     // pev_ holds a timed chunk not yet added to ktimes_
   KernelTimes ktimes_;
 };
 
@@ -1139,28 +1140,33 @@ void Engine<T>::launch_chunk() {
   const int CH = opt_.chunk;
   const bool prof = opt_.profile > 0 && (chunk_count_ % opt_.profile) == 0;
   ++chunk_count_;
+  if (prof) {
+    collect_times();  // the previous timed chunk (long finished) frees the event pool
+    if ((int)pev_.size() != 5 * CH) {
+      for (hipEvent_t e : pev_) (void)hipEventDestroy(e);
+      pev_.assign(5 * CH, nullptr);
+      for (auto& e : pev_) HIPCHECK(hipEventCreate(&e));
+    }
+  }
   auto enqueue = [&](bool timed) {
     tick_kernel<<<1, 1, 0, stream_>>>(d_gbase, (int64_t)CH);
     for (int i = 0; i < CH; ++i) {
-      hipEvent_t e[3] = {nullptr, nullptr, nullptr};
-      if (timed) {
-        for (int k = 0; k < 3; ++k) {
-          HIPCHECK(hipEventCreate(&e[k]));
-          pev_.push_back(e[k]);
-        }
-        HIPCHECK(hipEventRecord(e[0], stream_));
-      }
-      if (nPS_) slice_step<T><<<(unsigned)nPS_, kThreads, 0, stream_>>>(A, i, 0);
-      primal_step<T><<<(unsigned)nP_, kThreads, 0, stream_>>>(A, i);
+      hipEvent_t* e = timed ? &pev_[5 * i] : nullptr;
+      if (timed) HIPCHECK(hipEventRecord(e[0], stream_));
+      if (nPS_) primal_slice_step<T><<<(unsigned)nPS_, kThreads, 0, stream_>>>(A, i);
       if (timed) HIPCHECK(hipEventRecord(e[1], stream_));
-      if (nDS_) slice_step<T><<<(unsigned)nDS_, kThreads, 0, stream_>>>(A, i, 1);
-      dual_step<T><<<(unsigned)nD_, kThreads, 0, stream_>>>(A, i);
+      primal_step<T><<<(unsigned)nP_, kThreads, 0, stream_>>>(A, i);
       if (timed) HIPCHECK(hipEventRecord(e[2], stream_));
+      if (nDS_) dual_slice_step<T><<<(unsigned)nDS_, kThreads, 0, stream_>>>(A, i);
+      if (timed) HIPCHECK(hipEventRecord(e[3], stream_));
+      dual_step<T><<<(unsigned)nD_, kThreads, 0, stream_>>>(A, i);
+      if (timed) HIPCHECK(hipEventRecord(e[4], stream_));
     }
   };
   if (prof) {
     enqueue(true);
     HIPCHECK(hipGetLastError());
+    pev_pending_ = true;
   } else if (opt_.use_graph) {
     if (!gexec_) {
       HIPCHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
@@ -1178,18 +1184,18 @@ void Engine<T>::launch_chunk() {
 
 template <class T>
 void Engine<T>::collect_times() {
-  if (pev_.empty()) return;
-  HIPCHECK(hipStreamSynchronize(stream_));
-  for (size_t k = 0; k + 2 < pev_.size(); k += 3) {
-    float a = 0.f, b = 0.f;
-    HIPCHECK(hipEventElapsedTime(&a, pev_[k], pev_[k + 1]));
-    HIPCHECK(hipEventElapsedTime(&b, pev_[k + 1], pev_[k + 2]));
-    ktimes_.primal_ms += a;
-    ktimes_.dual_ms += b;
+  if (!pev_pending_) return;
+  HIPCHECK(hipEventSynchronize(pev_.back()));
+  for (size_t k = 0; k + 4 < pev_.size(); k += 5) {
+    float d[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 4; ++q) HIPCHECK(hipEventElapsedTime(&d[q], pev_[k + q], pev_[k + q + 1]));
+    ktimes_.primal_slice_ms += d[0];
+    ktimes_.primal_ms += d[1];
+    ktimes_.dual_slice_ms += d[2];
+    ktimes_.dual_ms += d[3];
     ktimes_.launches += 1;
   }
-  for (hipEvent_t e : pev_) (void)hipEventDestroy(e);
-  pev_.clear();
+  pev_pending_ = false;
 }
 
 template <class T>

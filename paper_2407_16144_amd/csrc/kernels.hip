@@ -381,8 +381,8 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
 // spart for the step kernel of the same step to add up).  dual = 1: rows of
 // K gathering xbar (or xT, cx1, cx2 at an eval step); dual = 0: rows of K^T
 // gathering y (or yT, cy1, cy2).
-template <class T>
-__global__ __launch_bounds__(kThreads) void slice_step(IterArgs<T> A, int step, int dual) {
+template <class T, bool dual>
+__device__ __forceinline__ void slice_body(const IterArgs<T>& A, int step) {
   __shared__ T s_prod[kSliceNB];
   __shared__ T s_rsum[3][kMaxRows];
   __shared__ int s_rp[kMaxRows + 1];
@@ -413,6 +413,16 @@ __global__ __launch_bounds__(kThreads) void slice_step(IterArgs<T> A, int step, 
   const int sl = blk_slice(b);
   for (int r = threadIdx.x; r < nrows; r += kThreads)
     for (int a = 0; a < nv; ++a) spart[(int64_t)(a * kSlices + sl) * space + b.r0 + r] = s_rsum[a][r];
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void primal_slice_step(IterArgs<T> A, int step) {
+  slice_body<T, false>(A, step);
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void dual_slice_step(IterArgs<T> A, int step) {
+  slice_body<T, true>(A, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,8 +1135,10 @@ template __global__ void primal_step<double>(IterArgs<double>, int);
 template __global__ void primal_step<float>(IterArgs<float>, int);
 template __global__ void dual_step<double>(IterArgs<double>, int);
 template __global__ void dual_step<float>(IterArgs<float>, int);
-template __global__ void slice_step<double>(IterArgs<double>, int, int);
-template __global__ void slice_step<float>(IterArgs<float>, int, int);
+template __global__ void primal_slice_step<double>(IterArgs<double>, int);
+template __global__ void primal_slice_step<float>(IterArgs<float>, int);
+template __global__ void dual_slice_step<double>(IterArgs<double>, int);
+template __global__ void dual_slice_step<float>(IterArgs<float>, int);
 template __global__ void cast_kernel<float>(const double*, float*, int64_t);
 template __global__ void scale_primal_kernel<double>(const Blk*, const double*, const double*,
                                                      const double*, const double*, double*, double*,

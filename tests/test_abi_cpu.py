@@ -48,6 +48,7 @@ def test_struct_layouts_match_header():
     assert fields("lp_options") == [f for f, _ in halp.lp_options._fields_]
     assert fields("lp_result") == [f for f, _ in halp.lp_result._fields_]
     assert fields("lp_problem") == [f for f, _ in halp.lp_problem._fields_]
+    assert fields("lp_kernel_timing") == [f for f, _ in halp.lp_kernel_timing._fields_]
 
 
 def test_default_options():
