@@ -170,6 +170,8 @@ typedef struct {
   double primal_ms;          /* primal_step: K^T y and the x half of eq. (pdhg) + Halpern blend */
   double dual_slice_ms;
   double dual_ms;            /* dual_step: K(2x+ - x), the y half of eq. (pdhg), controller */
+  double event_pair_ms;      /* two events recorded back to back (no kernel between):
+                                the timing overhead contained in each figure above */
   int64_t steps;             /* number of timed steps */
 } lp_kernel_timing;
 

@@ -60,7 +60,8 @@ class lp_result(C.Structure):
 
 class lp_kernel_timing(C.Structure):
     _fields_ = [("primal_slice_ms", C.c_double), ("primal_ms", C.c_double),
-                ("dual_slice_ms", C.c_double), ("dual_ms", C.c_double), ("steps", C.c_int64)]
+                ("dual_slice_ms", C.c_double), ("dual_ms", C.c_double), ("event_pair_ms", C.c_double),
+                ("steps", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -381,6 +381,7 @@ int lp_kernel_times(const lp_solver* s, lp_kernel_timing* out) {
     out->primal_ms = t.primal_ms;
     out->dual_slice_ms = t.dual_slice_ms;
     out->dual_ms = t.dual_ms;
+    out->event_pair_ms = t.event_pair_ms;
     out->steps = t.launches;
     return LP_OK;
   });
@@ -466,6 +467,7 @@ int lp_batch_kernel_times(const lp_batch* b, lp_kernel_timing* out) {
     out->primal_ms = t.primal_ms;
     out->dual_slice_ms = t.dual_slice_ms;
     out->dual_ms = t.dual_ms;
+    out->event_pair_ms = t.event_pair_ms;
     out->steps = t.launches;
     return LP_OK;
   });

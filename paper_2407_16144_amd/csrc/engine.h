@@ -55,7 +55,8 @@ struct Options {
 // kernel runs only where a product is column-sliced (else its sum stays 0).
 struct KernelTimes {
   double primal_slice_ms = 0.0, primal_ms = 0.0, dual_slice_ms = 0.0, dual_ms = 0.0;
-  int64_t launches = 0;  // timed steps
+  double event_pair_ms = 0.0;  // two events recorded back to back: included in every figure above
+  int64_t launches = 0;        // timed steps
 };
 
 struct Result {

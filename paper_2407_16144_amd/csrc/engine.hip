@@ -328,8 +328,9 @@ class Engine final : public EngineBase {
   hipGraph_t graph_ = nullptr;
   std::vector<InstState> h_st_;
   int64_t chunk_count_ = 0;
-  std::vector<hipEvent_t> pev_;  // 5 events per step of one chunk, reused by each timed chunk
+  std::vector<hipEvent_t> pev_;  // 6 events per step of one chunk, reused by each timed chunk
   bool pev_pending_ = false;     // pev_ holds a timed chunk not yet added to ktimes_
+  bool pev_slices_[2] = {false, false};  // the timed chunk launched primal / dual slice kernels
   KernelTimes ktimes_;
 };
 
@@ -1142,16 +1143,16 @@ void Engine<T>::launch_chunk() {
   ++chunk_count_;
   if (prof) {
     collect_times();  // the previous timed chunk (long finished) frees the event pool
-    if ((int)pev_.size() != 5 * CH) {
+    if ((int)pev_.size() != 6 * CH) {
       for (hipEvent_t e : pev_) (void)hipEventDestroy(e);
-      pev_.assign(5 * CH, nullptr);
+      pev_.assign(6 * CH, nullptr);
       for (auto& e : pev_) HIPCHECK(hipEventCreate(&e));
     }
   }
   auto enqueue = [&](bool timed) {
     tick_kernel<<<1, 1, 0, stream_>>>(d_gbase, (int64_t)CH);
     for (int i = 0; i < CH; ++i) {
-      hipEvent_t* e = timed ? &pev_[5 * i] : nullptr;
+      hipEvent_t* e = timed ? &pev_[6 * i] : nullptr;
       if (timed) HIPCHECK(hipEventRecord(e[0], stream_));
       if (nPS_) primal_slice_step<T><<<(unsigned)nPS_, kThreads, 0, stream_>>>(A, i);
       if (timed) HIPCHECK(hipEventRecord(e[1], stream_));
@@ -1160,13 +1161,18 @@ void Engine<T>::launch_chunk() {
       if (nDS_) dual_slice_step<T><<<(unsigned)nDS_, kThreads, 0, stream_>>>(A, i);
       if (timed) HIPCHECK(hipEventRecord(e[3], stream_));
       dual_step<T><<<(unsigned)nD_, kThreads, 0, stream_>>>(A, i);
-      if (timed) HIPCHECK(hipEventRecord(e[4], stream_));
+      if (timed) {
+        HIPCHECK(hipEventRecord(e[4], stream_));
+        HIPCHECK(hipEventRecord(e[5], stream_));  // empty pair: the events' own cost
+      }
     }
   };
   if (prof) {
     enqueue(true);
     HIPCHECK(hipGetLastError());
     pev_pending_ = true;
+    pev_slices_[0] = nPS_ > 0;
+    pev_slices_[1] = nDS_ > 0;
   } else if (opt_.use_graph) {
     if (!gexec_) {
       HIPCHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
@@ -1186,13 +1192,16 @@ template <class T>
 void Engine<T>::collect_times() {
   if (!pev_pending_) return;
   HIPCHECK(hipEventSynchronize(pev_.back()));
-  for (size_t k = 0; k + 4 < pev_.size(); k += 5) {
-    float d[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int q = 0; q < 4; ++q) HIPCHECK(hipEventElapsedTime(&d[q], pev_[k + q], pev_[k + q + 1]));
-    ktimes_.primal_slice_ms += d[0];
+  for (size_t k = 0; k + 5 < pev_.size(); k += 6) {
+    float d[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < 5; ++q) HIPCHECK(hipEventElapsedTime(&d[q], pev_[k + q], pev_[k + q + 1]));
+    // an event pair around a kernel that was not launched measures only the
+    // events' own overhead: count it as no time
+    if (pev_slices_[0]) ktimes_.primal_slice_ms += d[0];
     ktimes_.primal_ms += d[1];
-    ktimes_.dual_slice_ms += d[2];
+    if (pev_slices_[1]) ktimes_.dual_slice_ms += d[2];
     ktimes_.dual_ms += d[3];
+    ktimes_.event_pair_ms += d[4];
     ktimes_.launches += 1;
   }
   pev_pending_ = false;

@@ -138,6 +138,8 @@ def main(argv=None):
     t = traffic(args.fetch, args.write, args.copy_kernel, args.copy_bytes)
     print(traffic_table(t, args.only))
     if args.json:
+        if args.only:
+            t["kernels"] = {k: v for k, v in t["kernels"].items() if any(n in k for n in args.only)}
         t["source_sha256"] = kernel_source_hash()
         t["workload"] = args.workload
         with open(args.json, "w") as fh:
