@@ -284,6 +284,8 @@ def main():
                     help="first run a plain streaming kernel (y = -x, FP64) over this many MB "
                          "(calibration of the HBM byte counters)")
     ap.add_argument("--no-graph", action="store_true", help="launch steps without hipGraphs")
+    ap.add_argument("--cache-budget-mb", type=float, default=None,
+                    help="bytes (MiB) of vectors and tiles kept in the last-level cache (< 0: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})",
@@ -319,7 +321,8 @@ def main():
     opt = halp.lp_default_options(
         method=halp.LP_METHOD_R2HPDHG if args.method == "r2hpdhg" else halp.LP_METHOD_RHPDHG,
         precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64,
-        profile=args.profile_every, verbose=args.verbose, use_graph=0 if args.no_graph else 1)
+        profile=args.profile_every, verbose=args.verbose, use_graph=0 if args.no_graph else 1,
+        **({} if args.cache_budget_mb is None else {"cache_budget_bytes": int(args.cache_budget_mb * 2**20)}))
 
     def step():
         h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,

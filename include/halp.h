@@ -102,6 +102,10 @@ typedef struct {
                                tolerance, then continue in FP64 from the FP32
                                candidate (same scaling and step) to the request */
   int verbose;              /* k > 0: progress line on stderr every k seconds of a solve */
+  int64_t cache_budget_bytes; /* bytes of vectors and matrix tiles meant to stay in the
+                               last-level cache between steps (default 208 MiB of the
+                               256 MB Infinity Cache); the remaining tiles are read with
+                               non-temporal loads; < 0: every tile read normally */
 } lp_options;
 
 typedef struct {

@@ -43,7 +43,7 @@ class lp_options(C.Structure):
                 ("primal_weight", C.c_int), ("seed", C.c_uint64), ("eta", C.c_double),
                 ("omega0", C.c_double), ("chunk", C.c_int), ("use_graph", C.c_int),
                 ("profile", C.c_int), ("slice_min_bytes", C.c_int64), ("polish_tol", C.c_double),
-                ("verbose", C.c_int)]
+                ("verbose", C.c_int), ("cache_budget_bytes", C.c_int64)]
 
 
 class lp_result(C.Structure):

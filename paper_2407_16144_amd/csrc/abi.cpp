@@ -61,6 +61,7 @@ halp::Options to_opts(const lp_options* o) {
   r.slice_min_bytes = o->slice_min_bytes;
   r.polish_tol = o->polish_tol;
   r.verbose = o->verbose;
+  r.cache_budget_bytes = o->cache_budget_bytes;
   return r;
 }
 
@@ -264,6 +265,7 @@ void lp_default_options(lp_options* o) {
   o->slice_min_bytes = d.slice_min_bytes;
   o->polish_tol = d.polish_tol;
   o->verbose = d.verbose;
+  o->cache_budget_bytes = d.cache_budget_bytes;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }

@@ -48,6 +48,9 @@ struct Options {
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
   int64_t slice_min_bytes = 2 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
   double polish_tol = 1e-6;  // fp32: solve to this tolerance in fp32, then polish in fp64
+  // bytes of vectors and matrix tiles the step kernels keep in the last-level
+  // (Infinity) cache; tiles beyond it are read with non-temporal loads (< 0: all cached)
+  int64_t cache_budget_bytes = 208ll << 20;
   int verbose = 0;
 };
 

@@ -274,6 +274,8 @@ class Engine final : public EngineBase {
   void allocate();
   void release_all();
   void rebuild_schedules();
+  void mark_streaming(const std::vector<int>& live, std::vector<Blk>& P, std::vector<Blk>& PS,
+                      std::vector<Blk>& DS, std::vector<Blk>& D) const;
   int scheduled_ = 0;          // LPs in the current schedules
   bool compacted_ = false;     // current schedules leave finished LPs out
   const int* finished_ = nullptr;  // status words used to leave finished LPs out (compaction)
@@ -1065,6 +1067,38 @@ void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_
   for (int k = 0; k < ni; ++k) h_status[0][ids[k]] = h_status[1][ids[k]] = cur[k].status;
 }
 
+// The vectors of a step and the matrix tiles read before the cache budget is
+// used up are read normally and stay in the last-level cache from one step to
+// the next; the remaining tiles are streamed with non-temporal loads, so that
+// they do not evict what fits.  (A matrix pair larger than the cache read
+// round-robin would otherwise evict every line before its next use.)
+template <class T>
+void Engine<T>::mark_streaming(const std::vector<int>& live, std::vector<Blk>& P, std::vector<Blk>& PS,
+                               std::vector<Blk>& DS, std::vector<Blk>& D) const {
+  const int64_t budget = opt_.cache_budget_bytes;
+  int64_t used = 0;
+  for (int s : live) {
+    const Slot& sl = slots_[s];
+    // n-space: c, l, u, x, x0, xbar; m-space: q, y, y0; row pointers; slice partial sums
+    used += (int64_t)sizeof(T) * (6 * sl.n + 3 * sl.m) + 4 * (sl.n + sl.m);
+    if (!sl.bDS.empty()) used += (int64_t)(sizeof(T) + 4) * kSlices * sl.m;
+    if (!sl.bPS.empty()) used += (int64_t)(sizeof(T) + 4) * kSlices * sl.n;
+  }
+  auto mark = [&](std::vector<Blk>& v) {
+    for (Blk& k : v) {
+      k.meta &= ~kBlkNT;
+      if (blk_kind(k) == BK_PAD) continue;
+      const int64_t bytes = (int64_t)k.pn * (int64_t)(sizeof(T) + 4);
+      if (budget >= 0 && used + bytes > budget) k.meta |= kBlkNT;
+      else used += bytes;
+    }
+  };
+  mark(P);
+  mark(PS);
+  mark(DS);
+  mark(D);
+}
+
 template <class T>
 void Engine<T>::rebuild_schedules() {
   std::vector<Blk> P, D, PS, DS;
@@ -1092,6 +1126,7 @@ void Engine<T>::rebuild_schedules() {
     live.push_back(s);
     rg.push_back(r);
   }
+  mark_streaming(live, P, PS, DS, D);
   HIPCHECK(hipStreamSynchronize(stream_));
   auto upload = [&](std::vector<Blk>& v, Blk*& d, int64_t& cap, int64_t& n, double** part) {
     if ((int64_t)v.size() > cap) {

@@ -41,7 +41,9 @@ enum Status : int { ST_RUNNING = 0, ST_OPTIMAL = 1, ST_PRIMAL_INFEAS = 2, ST_DUA
 // a sliced row group (nsl = kSlices) cover the same rows, block `slice`
 // holding only the entries whose column falls in that slice, with its own
 // row pointers at brp[rp_off].  gid numbers row groups (partial sums and
-// arrival counters); meta packs kind | nsl << 8 | slice << 16.
+// arrival counters); meta packs kind | nsl << 8 | slice << 16, and kBlkNT
+// marks a block whose entries are read with non-temporal loads (they are not
+// meant to stay in the last-level cache: see the cache budget of Options).
 struct Blk {
   int32_t r0, r1, inst, meta;
   int32_t gid, rp_off, p0, pn;
@@ -50,6 +52,8 @@ struct Blk {
 __host__ __device__ inline int blk_kind(const Blk& b) { return b.meta & 0xff; }
 __host__ __device__ inline int blk_nsl(const Blk& b) { return (b.meta >> 8) & 0xff; }
 __host__ __device__ inline int blk_slice(const Blk& b) { return (b.meta >> 16) & 0xff; }
+constexpr int32_t kBlkNT = 1 << 24;
+__host__ __device__ inline bool blk_nt(const Blk& b) { return (b.meta & kBlkNT) != 0; }
 __host__ __device__ inline int32_t blk_meta(int kind, int nsl, int slice) {
   return kind | (nsl << 8) | (slice << 16);
 }

@@ -108,7 +108,9 @@ struct TileRegs {
   static constexpr int EPT = NB / kThreads;
   int cidx[EPT];
   T v[EPT];
-  T p[EPT];  // products with a gathered vector
+  T p[EPT];      // products with a gathered vector
+  int rpv = 0;   // row pointer t of the block (relative to p0), t = thread
+  int rpv2 = 0;  // row pointer kThreads (thread 0, blocks of kThreads rows)
 };
 
 // Products with the step's usual gathered vector, issued before the LP
@@ -123,25 +125,64 @@ __device__ __forceinline__ void spec_products(const Blk& b, const T* __restrict_
   }
 }
 
-// Loads a stream block's entries (coalesced) into registers; independent of
-// the step mode, so callers issue it before reading the LP state.
-template <class T, int NB>
-__device__ __forceinline__ void load_tile(const Blk& b, const int32_t* __restrict__ ci,
-                                          const T* __restrict__ val, TileRegs<T, NB>& R) {
-  if (blk_kind(b) != BK_STREAM) return;
+// Loads a stream block's entries (coalesced) and row pointers into
+// registers; independent of the step mode, so callers issue it before
+// reading the LP state.  rp points at the block's first row pointer.
+template <bool NT, class V>
+__device__ __forceinline__ V ld_entry(const V* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <bool NT, class T, int NB>
+__device__ __forceinline__ void load_tile_as(const Blk& b, const int32_t* __restrict__ rp,
+                                             const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                             TileRegs<T, NB>& R) {
+  const int t = threadIdx.x;
+  const int nrows = b.r1 - b.r0;
 #pragma unroll
   for (int k = 0; k < TileRegs<T, NB>::EPT; ++k) {
-    const int e = (int)threadIdx.x + k * kThreads;
+    const int e = t + k * kThreads;
     if (e < b.pn) {
-      R.cidx[k] = ci[b.p0 + e];
-      R.v[k] = val[b.p0 + e];
+      R.cidx[k] = ld_entry<NT>(ci + b.p0 + e);
+      R.v[k] = ld_entry<NT>(val + b.p0 + e);
     }
   }
+  if (t <= nrows) R.rpv = rp[t] - b.p0;
+  if (nrows == kThreads && t == 0) R.rpv2 = rp[kThreads] - b.p0;
+}
+
+// Loads a stream block's entries (coalesced) and row pointers into
+// registers; independent of the step mode, so callers issue it before
+// reading the LP state.  rp points at the block's first row pointer.
+template <class T, int NB>
+__device__ __forceinline__ void load_tile(const Blk& b, const int32_t* __restrict__ rp,
+                                          const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                          TileRegs<T, NB>& R) {
+  if (blk_kind(b) != BK_STREAM) return;
+  if (blk_nt(b)) load_tile_as<true, T, NB>(b, rp, ci, val, R);
+  else load_tile_as<false, T, NB>(b, rp, ci, val, R);
+}
+
+// Strided partial sums of one long row (entries [p0, p0 + pn)).
+template <bool NT, class T>
+__device__ __forceinline__ T long_row_sum(int p0, int pn, const int32_t* __restrict__ ci,
+                                          const T* __restrict__ val, const T* __restrict__ src) {
+  T acc0 = (T)0, acc1 = (T)0;
+  int e = threadIdx.x;
+  for (; e + kThreads < pn; e += 2 * kThreads) {
+    const int c0 = ld_entry<NT>(ci + p0 + e), c1 = ld_entry<NT>(ci + p0 + e + kThreads);
+    const T v0 = ld_entry<NT>(val + p0 + e), v1 = ld_entry<NT>(val + p0 + e + kThreads);
+    acc0 += v0 * src[c0];
+    acc1 += v1 * src[c1];
+  }
+  if (e < pn) acc0 += ld_entry<NT>(val + p0 + e) * src[ld_entry<NT>(ci + p0 + e)];
+  return acc0 + acc1;
 }
 
 // One gathered vector: row sums into out[r - b.r0] (LDS).
 template <class T, int NB>
-__device__ void block_spmv1(const Blk& b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+__device__ void block_spmv1(const Blk& b, const int32_t* __restrict__ ci,
                             const T* __restrict__ val, const TileRegs<T, NB>& R, const T* __restrict__ src,
                             T* s_prod, T* out, int* s_rp, double (*s_red)[kNS], T scale = (T)1,
                             bool have_products = false) {
@@ -149,16 +190,7 @@ __device__ void block_spmv1(const Blk& b, const int32_t* __restrict__ rp, const 
   const int nrows = b.r1 - b.r0;
   const int p0 = b.p0, pn = b.pn;
   if (blk_kind(b) == BK_LONG) {
-    T acc0 = (T)0, acc1 = (T)0;
-    int e = tid;
-    for (; e + kThreads < pn; e += 2 * kThreads) {
-      const int c0 = ci[p0 + e], c1 = ci[p0 + e + kThreads];
-      const T v0 = val[p0 + e], v1 = val[p0 + e + kThreads];
-      acc0 += v0 * src[c0];
-      acc1 += v1 * src[c1];
-    }
-    if (e < pn) acc0 += val[p0 + e] * src[ci[p0 + e]];
-    T t = wave_sum(acc0 + acc1);
+    T t = wave_sum(blk_nt(b) ? long_row_sum<true>(p0, pn, ci, val, src) : long_row_sum<false>(p0, pn, ci, val, src));
     if ((tid & 63) == 0) s_red[tid >> 6][0] = (double)t;
     lds_barrier();
     if (tid == 0) {
@@ -171,7 +203,8 @@ __device__ void block_spmv1(const Blk& b, const int32_t* __restrict__ rp, const 
     return;
   }
   constexpr int EPT = TileRegs<T, NB>::EPT;
-  for (int i = tid; i <= nrows; i += kThreads) s_rp[i] = rp[i] - p0;
+  if (tid <= nrows) s_rp[tid] = R.rpv;
+  if (nrows == kThreads && tid == 0) s_rp[kThreads] = R.rpv2;
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int e = tid + k * kThreads;
@@ -196,15 +229,15 @@ __device__ void block_spmv1(const Blk& b, const int32_t* __restrict__ rp, const 
 
 // NV gathered vectors, one after the other over the same register tile
 template <class T, int NV, int NB>
-__device__ __forceinline__ void block_spmv_regs(const Blk& b, const int32_t* __restrict__ rp,
+__device__ __forceinline__ void block_spmv_regs(const Blk& b,
                                                 const int32_t* __restrict__ ci, const T* __restrict__ val,
                                                 const TileRegs<T, NB>& R, const T* __restrict__ s0,
                                                 const T* __restrict__ s1, const T* __restrict__ s2, T* s_prod,
                                                 T (*s_rsum)[kMaxRows], int* s_rp, double (*s_red)[kNS],
                                                 T scale0 = (T)1) {
-  block_spmv1<T, NB>(b, rp, ci, val, R, s0, s_prod, s_rsum[0], s_rp, s_red, scale0);
-  if constexpr (NV > 1) block_spmv1<T, NB>(b, rp, ci, val, R, s1, s_prod, s_rsum[1], s_rp, s_red);
-  if constexpr (NV > 2) block_spmv1<T, NB>(b, rp, ci, val, R, s2, s_prod, s_rsum[2], s_rp, s_red);
+  block_spmv1<T, NB>(b, ci, val, R, s0, s_prod, s_rsum[0], s_rp, s_red, scale0);
+  if constexpr (NV > 1) block_spmv1<T, NB>(b, ci, val, R, s1, s_prod, s_rsum[1], s_rp, s_red);
+  if constexpr (NV > 2) block_spmv1<T, NB>(b, ci, val, R, s2, s_prod, s_rsum[2], s_rp, s_red);
 }
 
 template <class T, int NV>
@@ -214,8 +247,8 @@ __device__ __forceinline__ void block_spmv(const Blk& b, const int32_t* __restri
                                            const T* __restrict__ s2, T* s_prod, T (*s_rsum)[kMaxRows],
                                            int* s_rp, double (*s_red)[kNS], T scale0 = (T)1) {
   TileRegs<T, kPlainNB> R;
-  load_tile<T, kPlainNB>(b, ci, val, R);
-  block_spmv_regs<T, NV, kPlainNB>(b, rp, ci, val, R, s0, s1, s2, s_prod, s_rsum, s_rp, s_red, scale0);
+  load_tile<T, kPlainNB>(b, rp, ci, val, R);
+  block_spmv_regs<T, NV, kPlainNB>(b, ci, val, R, s0, s1, s2, s_prod, s_rsum, s_rp, s_red, scale0);
 }
 
 // Row sums of a sliced row group: the kSlices partial sums written by the
@@ -226,7 +259,10 @@ __device__ __forceinline__ void gather_slices(const Blk& b, const T* __restrict_
   const int nrows = b.r1 - b.r0;
   const int t = threadIdx.x;
   if (t < nrows) {
-#pragma unroll
+    // one vector at a time: its kSlices loads in flight together, but not
+    // the NV * kSlices of all vectors (they would set the register budget
+    // of the whole step kernel)
+#pragma unroll 1
     for (int a = 0; a < NV; ++a) {
       T acc = (T)0;
 #pragma unroll
@@ -283,7 +319,7 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
   // entries and epilogue operands are loaded before the LP state is read,
   // so their latency overlaps the state loads (none depends on the mode)
   TileRegs<T, kPlainNB> R;
-  load_tile<T, kPlainNB>(b, A.KT_ci, A.KT_v, R);
+  load_tile<T, kPlainNB>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R);
   spec_products<T, kPlainNB>(b, A.y, R);
   T cj = 0, lj = 0, uj = 0, xo = 0, x0j = 0, kty = 0;
   if (own) {
@@ -307,11 +343,9 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartP, A.NS, s_rsum);
     else if (!resid) gather_slices<T, 1>(b, A.spartP, A.NS, s_rsum);
   } else if (mode == M_EVAL) {
-    block_spmv_regs<T, 3, kPlainNB>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp,
-                          s_red);
+    block_spmv_regs<T, 3, kPlainNB>(b, A.KT_ci, A.KT_v, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
   } else if (!resid) {
-    block_spmv1<T, kPlainNB>(b, A.KT_rp + b.r0, A.KT_ci, A.KT_v, R, A.y, s_prod, s_rsum[0], s_rp, s_red, (T)1,
-                             true);
+    block_spmv1<T, kPlainNB>(b, A.KT_ci, A.KT_v, R, A.y, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
   }
 
   double ps[kNS];
@@ -393,7 +427,7 @@ __device__ __forceinline__ void slice_body(const IterArgs<T>& A, int step) {
   const int32_t* ci = dual ? A.K_ci : A.KT_ci;
   const T* val = dual ? A.K_v : A.KT_v;
   TileRegs<T, kSliceNB> R;
-  load_tile<T, kSliceNB>(b, ci, val, R);
+  load_tile<T, kSliceNB>(b, rp, ci, val, R);
   const T* src = dual ? A.xbar : A.y;
   spec_products<T, kSliceNB>(b, src, R);
   const InstState& S = A.st[b.inst];
@@ -404,10 +438,10 @@ __device__ __forceinline__ void slice_body(const IterArgs<T>& A, int step) {
   const int64_t space = dual ? A.MS : A.NS;
   const int nv = mode == M_EVAL ? 3 : 1;
   if (mode == M_EVAL) {
-    if (dual) block_spmv_regs<T, 3, kSliceNB>(b, rp, ci, val, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
-    else block_spmv_regs<T, 3, kSliceNB>(b, rp, ci, val, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+    if (dual) block_spmv_regs<T, 3, kSliceNB>(b, ci, val, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    else block_spmv_regs<T, 3, kSliceNB>(b, ci, val, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
   } else {
-    block_spmv1<T, kSliceNB>(b, rp, ci, val, R, src, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
+    block_spmv1<T, kSliceNB>(b, ci, val, R, src, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
   }
   const int nrows = b.r1 - b.r0;
   const int sl = blk_slice(b);
@@ -543,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
   const int64_t i = (int64_t)b.r0 + (own ? t : 0);
   // entries and epilogue operands are loaded before the LP state is read
   TileRegs<T, kPlainNB> R;
-  load_tile<T, kPlainNB>(b, A.K_ci, A.K_v, R);
+  load_tile<T, kPlainNB>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R);
   spec_products<T, kPlainNB>(b, A.xbar, R);
   T qi = 0, yo = 0, y0i = 0, kxpi = 0;
   if (own) {
@@ -565,9 +599,9 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartD, A.MS, s_rsum);
     else gather_slices<T, 1>(b, A.spartD, A.MS, s_rsum);
   } else if (mode == M_EVAL) {
-    block_spmv_regs<T, 3, kPlainNB>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    block_spmv_regs<T, 3, kPlainNB>(b, A.K_ci, A.K_v, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
   } else {
-    block_spmv1<T, kPlainNB>(b, A.K_rp + b.r0, A.K_ci, A.K_v, R, A.xbar, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
+    block_spmv1<T, kPlainNB>(b, A.K_ci, A.K_v, R, A.xbar, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
   }
 
   double ps[kNS];
