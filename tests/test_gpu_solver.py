@@ -232,6 +232,24 @@ def test_graph_and_stream_launch_agree(graph):
     assert np.array_equal(x, x2) and np.array_equal(y, y2)
 
 
+
+@pytest.mark.parametrize("sliced,budget", [(False, 0), (True, 0), (False, 150_000), (True, 330_000)])
+def test_streamed_tiles_give_identical_iterates(sliced, budget):
+    """Matrix tiles past the cache budget are read with non-temporal loads:
+    the values (and so every iterate) are the same bits as with all tiles
+    cached.  Budget 0 streams every tile; the other budgets exceed the
+    vectors of this LP (~90 kB, ~270 kB with the slice partial sums) and
+    stream only part of the tiles."""
+    lp = lpgen.scaled_powerlaw(31, 400, 1500)
+    sl = 0 if sliced else -1
+    print(f"case streamed tiles sliced={sliced} budget={budget}", flush=True)
+    r1, x1, y1, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=sl, cache_budget_bytes=-1)
+    r2, x2, y2, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=sl, cache_budget_bytes=budget)
+    assert r1["iters"] == r2["iters"] and r1["restarts"] == r2["restarts"]
+    assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=1000))
+    assert _rel(x2, ref.x) <= 1e-10 and _rel(y2, ref.y) <= 1e-10
+
 def test_fp32_mode_reaches_moderate_accuracy():
     lp = lpgen.tiny()
     print("case fp32", flush=True)
