@@ -50,6 +50,27 @@ def kernel_bytes(n, m, nnz, s, primal_sliced, dual_sliced):
             "dual_step": depi + (0 if dual_sliced else dmat)}
 
 
+def batch_roofline(ksum, s):
+    """Roofline of the dominant step kernel of a batch from the library's
+    timings: per-kernel average durations (event-pair cost taken out) and the
+    average sizes of the LPs the timed steps processed (finished LPs leave the
+    schedules).  Small LPs are not column-sliced, so the two step kernels hold
+    the whole products."""
+    kn = max(ksum.get("steps", 0), 1)
+    ev = ksum.get("event_pair_ms", 0.0) / kn
+    avg = {k: max(ksum.get(k + "_ms", 0.0) / kn - ev, 0.0) for k in ("primal", "dual")}
+    nnz, n, m = (ksum.get(k, 0.0) / kn for k in ("nnz", "n", "m"))
+    pb, db = algorithmic_bytes(n, m, nnz, s)
+    byts = {"primal": pb, "dual": db}
+    dom = max(avg, key=lambda k: avg[k])
+    ach = byts[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom + "_step",
+            "bytes_per_launch": int(byts[dom]), "avg_ms": {k + "_step": round(v, 5) for k, v in avg.items()},
+            "avg_scheduled": {"nnz": round(nnz), "n": round(n), "m": round(m)},
+            "timed_steps": int(ksum.get("steps", 0)), "event_pair_ms": round(ev, 5)}
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     counter summary (profiles/traffic_<workload>.json: FETCH_SIZE and
@@ -151,17 +172,14 @@ def run_batch(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat = []
-    kt_ms = 0.0
-    kn = 0
+    ksum = {}
+    res = []
     for i in range(args.steps):
         s0 = time.perf_counter()
         res, kt = step()
         lat.append(time.perf_counter() - s0)
-        # kernel time of the timed steps, without the cost of their events
-        nk = 2 + (kt["primal_slice_ms"] > 0) + (kt["dual_slice_ms"] > 0)
-        kt_ms += (kt["primal_slice_ms"] + kt["primal_ms"] + kt["dual_slice_ms"] + kt["dual_ms"]
-                  - nk * kt["event_pair_ms"])
-        kn += kt["steps"]
+        for k, v in kt.items():
+            ksum[k] = ksum.get(k, 0.0) + v
         st = [r["status"] for r in res]
         print(f"batch step {i}: {lat[-1]:.2f}s optimal={st.count(1)} infeasible={st.count(2)} "
               f"limit={st.count(4)}", file=sys.stderr, flush=True)
@@ -169,9 +187,8 @@ def run_batch(args):
     wall = time.perf_counter() - t0
     solved = sum(r["status"] in (1, 2, 3) for r in res) * args.steps
     s = 8 if args.precision == "fp64" else 4
-    bytes_step = sum(sum(algorithmic_bytes(lp.n, lp.m, lp.nnz, s)) for lp in lps)
-    tstep = kt_ms / max(kn, 1)
-    ach = bytes_step / (tstep * 1e-3) / 1e9 if tstep > 0 else 0.0
+    roofline = batch_roofline(ksum, s)
+    st = [r["status"] for r in res]
     out = {"metric": "solved LPs/s + p99 latency at 1e-4 rel. KKT; SpMV HBM GB/s vs peak",
            "value": round(solved / wall, 3), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 1),
@@ -179,11 +196,11 @@ def run_batch(args):
            "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
            "config": {"workload": f"batch of {len(lps)} power-law LPs, {nnz} nnz total, tol {args.tol:g}",
                       "method": args.method, "precision": args.precision,
+                      "statuses": {"optimal": st.count(1), "primal_infeasible": st.count(2),
+                                   "dual_infeasible": st.count(3), "limit": st.count(4) + st.count(5)},
                       "max_iters": max(r["iters"] for r in res),
                       "p50_latency_s": round(_pct(lat, 0.5), 3), "p99_latency_s": round(_pct(lat, 0.99), 3)},
-           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": "primal_step+dual_step (whole step)", "timed_steps": kn}}
+           "roofline": roofline}
     if args.serial_baseline:
         k = min(args.serial_baseline, len(lps))
         sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)

@@ -98,14 +98,18 @@ typedef struct {
                                the vector its product gathers exceeds this many
                                bytes (default 2 MiB; < 0 never) */
   double polish_tol;        /* FP32 precision: when the requested tolerance is
-                               below this (default 1e-6), solve in FP32 to this
-                               tolerance, then continue in FP64 from the FP32
-                               candidate (same scaling and step) to the request */
+                               below this (default 1e-3), solve in FP32 to this
+                               tolerance (or to the stall rule), then continue in
+                               FP64 from the FP32 candidate (same scaling and step)
+                               to the request: lp_solve and lp_batch_solve */
   int verbose;              /* k > 0: progress line on stderr every k seconds of a solve */
   int64_t cache_budget_bytes; /* bytes of vectors and matrix tiles meant to stay in the
                                last-level cache between steps (default 208 MiB of the
                                256 MB Infinity Cache); the remaining tiles are read with
                                non-temporal loads; < 0: every tile read normally */
+  int64_t stall_checks;     /* FP32 phase of a polished solve: an LP moves on to the FP64
+                               phase after this many checks without a 10% drop of its
+                               best relative KKT error (default 200; 0: only at polish_tol) */
 } lp_options;
 
 typedef struct {
@@ -176,6 +180,8 @@ typedef struct {
   double dual_ms;            /* dual_step: K(2x+ - x), the y half of eq. (pdhg), controller */
   double event_pair_ms;      /* two events recorded back to back (no kernel between):
                                 the timing overhead contained in each figure above */
+  double nnz, n, m;          /* matrix entries, variables and rows of the LPs the timed
+                                steps processed, summed over those steps */
   int64_t steps;             /* number of timed steps */
 } lp_kernel_timing;
 

@@ -43,7 +43,7 @@ class lp_options(C.Structure):
                 ("primal_weight", C.c_int), ("seed", C.c_uint64), ("eta", C.c_double),
                 ("omega0", C.c_double), ("chunk", C.c_int), ("use_graph", C.c_int),
                 ("profile", C.c_int), ("slice_min_bytes", C.c_int64), ("polish_tol", C.c_double),
-                ("verbose", C.c_int), ("cache_budget_bytes", C.c_int64)]
+                ("verbose", C.c_int), ("cache_budget_bytes", C.c_int64), ("stall_checks", C.c_int64)]
 
 
 class lp_result(C.Structure):
@@ -61,7 +61,7 @@ class lp_result(C.Structure):
 class lp_kernel_timing(C.Structure):
     _fields_ = [("primal_slice_ms", C.c_double), ("primal_ms", C.c_double),
                 ("dual_slice_ms", C.c_double), ("dual_ms", C.c_double), ("event_pair_ms", C.c_double),
-                ("steps", C.c_int64)]
+                ("nnz", C.c_double), ("n", C.c_double), ("m", C.c_double), ("steps", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

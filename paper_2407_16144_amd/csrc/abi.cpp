@@ -8,6 +8,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/halp.h"
@@ -62,6 +63,7 @@ halp::Options to_opts(const lp_options* o) {
   r.polish_tol = o->polish_tol;
   r.verbose = o->verbose;
   r.cache_budget_bytes = o->cache_budget_bytes;
+  r.stall_checks = o->stall_checks;
   return r;
 }
 
@@ -147,6 +149,10 @@ struct StreamHolder {
   }
 };
 
+void hip_ok(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw halp::Error(LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -216,6 +222,98 @@ struct RawLP {
   }
 };
 
+namespace {
+
+// FP64 continuation of LPs that an FP32 engine solved to the polish
+// tolerance (or left at its precision floor: stall rule, iteration limit).
+// Each continues from its FP32 candidate T(z) in the same scaled space (both
+// engines compute the scaling and the step size in FP64 from the same inputs)
+// with the FP32 primal weight, as a fresh epoch, for the iterations left.
+struct Polish {
+  std::unique_ptr<halp::EngineBase> eng;
+  std::vector<int> id;                // per LP of the FP32 engine: FP64 id, or -1
+  std::vector<halp::Result> first;    // the FP32 phase's result of each polished LP
+};
+
+bool polish_wanted(const halp::Result& r, int64_t max_iter) {
+  const bool go = r.status == LP_OPTIMAL || r.status == LP_ITER_LIMIT || r.status == LP_NUMERICAL;
+  return go && r.iters < max_iter;
+}
+
+void run_polish(Polish& P, const halp::Options& opt, hipStream_t stream, halp::EngineBase& src,
+                const std::vector<int>& src_ids, const std::vector<const RawLP*>& raw, double tol,
+                int64_t max_iter, double left_s) {
+  const int count = (int)src_ids.size();
+  P.id.assign(count, -1);
+  P.first.assign(count, halp::Result());
+  std::vector<int> which;
+  int64_t ms = 0, ns = 0, zs = 0, buf_len = 1;
+  for (int i = 0; i < count; ++i) {
+    const halp::Result r = src.result(src_ids[i]);
+    if (!polish_wanted(r, max_iter)) continue;
+    which.push_back(i);
+    P.first[i] = r;
+    const lp_problem& p = raw[i]->view;
+    ms += p.m_eq + p.m_ineq + 1;
+    ns += p.n + 1;
+    zs += raw[i]->nnz;
+    buf_len = std::max<int64_t>(buf_len, p.n + p.m_eq + p.m_ineq + 1);
+  }
+  if (which.empty() || (left_s >= 0.0 && left_s <= 0.0)) return;
+  halp::Options o64 = opt;
+  o64.precision = 0;
+  P.eng = halp::make_engine(o64, stream, ms, ns, zs, (int)which.size());
+  std::vector<halp::Problem> probs;
+  for (int i : which) probs.push_back(to_problem(raw[i]->view));
+  const std::vector<int> ids = P.eng->add(probs, raw[which[0]]->on_device);
+  double* buf = nullptr;
+  if (hipMalloc((void**)&buf, sizeof(double) * buf_len) != hipSuccess)
+    throw halp::Error(LP_ERR_OOM, "device allocation failed");
+  try {
+    for (size_t k = 0; k < which.size(); ++k) {
+      const int i = which[k];
+      const lp_problem& p = raw[i]->view;
+      double omega = 1.0;
+      src.export_point(src_ids[i], buf, buf + p.n, &omega);
+      P.eng->import_point(ids[k], buf, buf + p.n, omega);
+      P.id[i] = ids[k];
+      P.eng->set_params({ids[k]}, tol, max_iter - P.first[i].iters);
+    }
+  } catch (...) {
+    (void)hipFree(buf);
+    throw;
+  }
+  (void)hipFree(buf);
+  P.eng->run(left_s);
+}
+
+// Engine and id holding LP i's final iterate: the FP64 continuation when it
+// was polished, else the FP32 engine.
+halp::EngineBase& final_engine(const Polish& P, int i, halp::EngineBase& src, int src_id, int* id) {
+  if (P.eng && i < (int)P.id.size() && P.id[i] >= 0) {
+    *id = P.id[i];
+    return *P.eng;
+  }
+  *id = src_id;
+  return src;
+}
+
+// Result of LP i: the FP64 continuation's (iterations and restarts of both
+// phases added) when it was polished, else the FP32 phase's.
+lp_result polish_result(const Polish& P, int i, halp::EngineBase& src, int src_id, double seconds) {
+  if (P.eng && i < (int)P.id.size() && P.id[i] >= 0) {
+    lp_result o = to_result(P.eng->result(P.id[i]), seconds);
+    o.polish_iters = o.iters;
+    o.iters += P.first[i].iters;
+    o.restarts += P.first[i].restarts;
+    o.checks += P.first[i].checks;
+    return o;
+  }
+  return to_result(src.result(src_id), seconds);
+}
+
+}  // namespace
+
 struct lp_solver {
   StreamHolder stream;
   halp::Options opt;
@@ -223,18 +321,19 @@ struct lp_solver {
   int id = -1;
   bool solved = false;
   double seconds = 0.0;
-  // FP32 mode: inputs kept for the FP64 polish, and the polish engine
+  // FP32 mode: inputs kept for the FP64 polish, and the polish stage
   std::unique_ptr<RawLP> raw;
-  std::unique_ptr<halp::EngineBase> eng64;
-  int id64 = -1;
-  halp::Result first;  // result of the FP32 phase when polished
+  Polish polish;
 };
 
 struct lp_batch {
   StreamHolder stream;
+  halp::Options opt;
   std::unique_ptr<halp::EngineBase> eng;
   std::vector<int> ids;
   double seconds = 0.0;
+  std::vector<std::unique_ptr<RawLP>> raw;  // FP32 mode: inputs kept for the FP64 polish
+  Polish polish;
 };
 
 extern "C" {
@@ -266,6 +365,7 @@ void lp_default_options(lp_options* o) {
   o->polish_tol = d.polish_tol;
   o->verbose = d.verbose;
   o->cache_budget_bytes = d.cache_budget_bytes;
+  o->stall_checks = d.stall_checks;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }
@@ -302,36 +402,11 @@ int lp_solve(lp_solver* s, double tol, int64_t max_iter, double time_limit_s) {
     if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
     const double t0 = now_s();
     const bool polish = s->raw && tol < s->opt.polish_tol;
-    s->eng->set_params({s->id}, polish ? s->opt.polish_tol : tol, max_iter);
+    s->eng->set_params({s->id}, polish ? s->opt.polish_tol : tol, max_iter, polish ? s->opt.stall_checks : 0);
     s->eng->run(time_limit_s);
     if (polish) {
-      // FP64 polish from the FP32 candidate, unless the FP32 phase already
-      // ended for good (infeasible, time limit)
-      const halp::Result r = s->eng->result(s->id);
-      const bool go = r.status == LP_OPTIMAL || r.status == LP_ITER_LIMIT || r.status == LP_NUMERICAL;
       const double left = time_limit_s < 0 ? -1.0 : time_limit_s - (now_s() - t0);
-      if (go && r.iters < max_iter && (time_limit_s < 0 || left > 0)) {
-        halp::Options o64 = s->opt;
-        o64.precision = 0;
-        const lp_problem& p = s->raw->view;
-        s->eng64 = halp::make_engine(o64, s->stream.s, p.m_eq + p.m_ineq + 1, p.n + 1, s->raw->nnz, 1);
-        s->id64 = s->eng64->add({to_problem(p)}, s->raw->on_device)[0];
-        double* buf = nullptr;
-        if (hipMalloc((void**)&buf, sizeof(double) * (p.n + p.m_eq + p.m_ineq + 1)) != hipSuccess)
-          throw halp::Error(LP_ERR_OOM, "device allocation failed");
-        double omega = 1.0;
-        try {
-          s->eng->export_point(s->id, buf, buf + p.n, &omega);
-          s->eng64->import_point(s->id64, buf, buf + p.n, omega);
-        } catch (...) {
-          (void)hipFree(buf);
-          throw;
-        }
-        (void)hipFree(buf);
-        s->first = r;
-        s->eng64->set_params({s->id64}, tol, max_iter - r.iters);
-        s->eng64->run(left);
-      }
+      run_polish(s->polish, s->opt, s->stream.s, *s->eng, {s->id}, {s->raw.get()}, tol, max_iter, left);
     }
     s->seconds = now_s() - t0;
     s->solved = true;
@@ -342,15 +417,7 @@ int lp_solve(lp_solver* s, double tol, int64_t max_iter, double time_limit_s) {
 int lp_status(const lp_solver* s, lp_result* out) {
   return guarded([&]() -> int {
     if (!s || !out) return fail(LP_ERR_INVALID, "null argument");
-    if (s->eng64) {
-      *out = to_result(s->eng64->result(s->id64), s->seconds);
-      out->polish_iters = out->iters;
-      out->iters += s->first.iters;
-      out->restarts += s->first.restarts;
-      out->checks += s->first.checks;
-    } else {
-      *out = to_result(s->eng->result(s->id), s->seconds);
-    }
+    *out = polish_result(s->polish, 0, *s->eng, s->id, s->seconds);
     return LP_OK;
   });
 }
@@ -359,8 +426,8 @@ int lp_get_solution(const lp_solver* s, double* x, double* y, int to_device) {
   return guarded([&]() -> int {
     if (!s) return fail(LP_ERR_INVALID, "null handle");
     if (!s->solved) return fail(LP_ERR_STATE, "solve first");
-    if (s->eng64) s->eng64->solution(s->id64, x, y, to_device != 0);
-    else s->eng->solution(s->id, x, y, to_device != 0);
+    int id = -1;
+    final_engine(s->polish, 0, *s->eng, s->id, &id).solution(id, x, y, to_device != 0);
     return LP_OK;
   });
 }
@@ -369,8 +436,8 @@ int lp_get_certificate(const lp_solver* s, double* ray, int to_device) {
   return guarded([&]() -> int {
     if (!s || !ray) return fail(LP_ERR_INVALID, "null argument");
     if (!s->solved) return fail(LP_ERR_STATE, "solve first");
-    if (s->eng64) s->eng64->certificate(s->id64, ray, to_device != 0);
-    else s->eng->certificate(s->id, ray, to_device != 0);
+    int id = -1;
+    final_engine(s->polish, 0, *s->eng, s->id, &id).certificate(id, ray, to_device != 0);
     return LP_OK;
   });
 }
@@ -384,6 +451,9 @@ int lp_kernel_times(const lp_solver* s, lp_kernel_timing* out) {
     out->dual_slice_ms = t.dual_slice_ms;
     out->dual_ms = t.dual_ms;
     out->event_pair_ms = t.event_pair_ms;
+    out->nnz = t.nnz;
+    out->n = t.n;
+    out->m = t.m;
     out->steps = t.launches;
     return LP_OK;
   });
@@ -418,8 +488,16 @@ int lp_batch_create(lp_batch** out, int count, const lp_problem* problems, int i
     if (zs > INT32_MAX) return fail(LP_ERR_INVALID, "batch holds more than 2^31 - 1 entries");
     std::unique_ptr<lp_batch> b(new lp_batch());
     b->stream.init(stream);
+    b->opt = o;
     b->eng = halp::make_engine(o, b->stream.s, ms, ns, zs, count);
     b->ids = b->eng->add(ps, inputs_on_device != 0);
+    if (o.precision == 1 && o.polish_tol > 0.0) {
+      for (int i = 0; i < count; ++i) {
+        b->raw.emplace_back(new RawLP());
+        b->raw.back()->capture(problems[i], read_nnz(problems[i], inputs_on_device != 0), inputs_on_device != 0,
+                               b->stream.s);
+      }
+    }
     *out = b.release();
     return LP_OK;
   });
@@ -430,8 +508,15 @@ int lp_batch_solve(lp_batch* b, double tol, int64_t max_iter, double time_limit_
     if (!b) return fail(LP_ERR_INVALID, "null handle");
     if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
     const double t0 = now_s();
-    b->eng->set_params(b->ids, tol, max_iter);
+    const bool polish = !b->raw.empty() && tol < b->opt.polish_tol;
+    b->eng->set_params(b->ids, polish ? b->opt.polish_tol : tol, max_iter, polish ? b->opt.stall_checks : 0);
     b->eng->run(time_limit_s);
+    if (polish) {
+      std::vector<const RawLP*> raw;
+      for (auto& r : b->raw) raw.push_back(r.get());
+      const double left = time_limit_s < 0 ? -1.0 : time_limit_s - (now_s() - t0);
+      run_polish(b->polish, b->opt, b->stream.s, *b->eng, b->ids, raw, tol, max_iter, left);
+    }
     b->seconds = now_s() - t0;
     return LP_OK;
   });
@@ -440,7 +525,7 @@ int lp_batch_solve(lp_batch* b, double tol, int64_t max_iter, double time_limit_
 int lp_batch_status(const lp_batch* b, int index, lp_result* out) {
   return guarded([&]() -> int {
     if (!b || !out || index < 0 || index >= (int)b->ids.size()) return fail(LP_ERR_INVALID, "bad argument");
-    *out = to_result(b->eng->result(b->ids[index]), b->seconds);
+    *out = polish_result(b->polish, index, *b->eng, b->ids[index], b->seconds);
     return LP_OK;
   });
 }
@@ -448,7 +533,8 @@ int lp_batch_status(const lp_batch* b, int index, lp_result* out) {
 int lp_batch_get_solution(const lp_batch* b, int index, double* x, double* y, int to_device) {
   return guarded([&]() -> int {
     if (!b || index < 0 || index >= (int)b->ids.size()) return fail(LP_ERR_INVALID, "bad argument");
-    b->eng->solution(b->ids[index], x, y, to_device != 0);
+    int id = -1;
+    final_engine(b->polish, index, *b->eng, b->ids[index], &id).solution(id, x, y, to_device != 0);
     return LP_OK;
   });
 }
@@ -456,7 +542,8 @@ int lp_batch_get_solution(const lp_batch* b, int index, double* x, double* y, in
 int lp_batch_get_certificate(const lp_batch* b, int index, double* ray, int to_device) {
   return guarded([&]() -> int {
     if (!b || !ray || index < 0 || index >= (int)b->ids.size()) return fail(LP_ERR_INVALID, "bad argument");
-    b->eng->certificate(b->ids[index], ray, to_device != 0);
+    int id = -1;
+    final_engine(b->polish, index, *b->eng, b->ids[index], &id).certificate(id, ray, to_device != 0);
     return LP_OK;
   });
 }
@@ -470,6 +557,9 @@ int lp_batch_kernel_times(const lp_batch* b, lp_kernel_timing* out) {
     out->dual_slice_ms = t.dual_slice_ms;
     out->dual_ms = t.dual_ms;
     out->event_pair_ms = t.event_pair_ms;
+    out->nnz = t.nnz;
+    out->n = t.n;
+    out->m = t.m;
     out->steps = t.launches;
     return LP_OK;
   });
@@ -501,12 +591,49 @@ struct Request {
   lp_result res{};
   double t_done = 0.0;
   std::vector<double> x, y;
+  // FP32 server with polish: the FP32 phase's candidate (scaled) and result,
+  // and the slot of the FP64 phase
+  std::vector<double> px, py;
+  double pomega = 1.0;
+  halp::Result first;
+  int slot64 = -1;
 };
+
+halp::Problem request_problem(const Request& r) {
+  halp::Problem q;
+  q.n = r.n;
+  q.m_eq = r.m_eq;
+  q.m_ineq = r.m_ineq;
+  q.rp = r.rp.data();
+  q.ci = r.ci.data();
+  q.val = r.val.data();
+  q.c = r.c.data();
+  q.rhs = r.rhs.data();
+  q.lb = r.lb.data();
+  q.ub = r.ub.data();
+  return q;
+}
+
+// engine capacities for a memory budget: the budget is split over the three
+// spaces for a reference mix of n = 4 m and nnz = 36 m (the batched sizes)
+bool server_caps(int64_t budget, int precision, int64_t* cap_m, int64_t* cap_n, int64_t* cap_nz) {
+  const int64_t sz = precision == 1 ? 4 : 8;
+  const int64_t per_row = 4 + 24 + 9 * sz, per_col = 4 + 40 + 10 * sz;
+  const int64_t per_nz = 24 + (precision == 1 ? 8 : 0);
+  const int64_t unit = per_row + 4 * per_col + 36 * per_nz;
+  const int64_t u = budget / unit;
+  if (u < 16) return false;
+  *cap_m = u;
+  *cap_n = 4 * u;
+  *cap_nz = std::min<int64_t>(36 * u, INT32_MAX - 1);
+  return true;
+}
 
 }  // namespace
 
 struct lp_server {
   StreamHolder stream;
+  halp::Options opt;
   std::unique_ptr<halp::EngineBase> eng;
   int64_t budget = 0;
   int max_slots = 0;
@@ -514,8 +641,28 @@ struct lp_server {
   std::deque<int64_t> queue;
   std::map<int64_t, Request> reqs;
   std::map<int, int64_t> slot_ticket;
+  // FP32 servers: the FP64 polish phase (its own engine, queue and slots)
+  std::unique_ptr<halp::EngineBase> eng64;
+  std::deque<int64_t> queue64;
+  std::map<int, int64_t> slot_ticket64;
+  double* dbuf = nullptr;  // device staging of candidates between the phases
+  int64_t dbuf_len = 0;
   double t0 = 0.0;
   double clock() const { return now_s() - t0; }
+  ~lp_server() {
+    if (dbuf) (void)hipFree(dbuf);
+  }
+  double* staging(int64_t len) {
+    if (len > dbuf_len) {
+      if (dbuf) (void)hipFree(dbuf);
+      dbuf = nullptr;
+      dbuf_len = 0;
+      if (hipMalloc((void**)&dbuf, sizeof(double) * len) != hipSuccess)
+        throw halp::Error(LP_ERR_OOM, "device allocation failed");
+      dbuf_len = len;
+    }
+    return dbuf;
+  }
 };
 
 extern "C" {
@@ -528,18 +675,19 @@ int lp_server_create(lp_server** out, int64_t budget, int max_slots, void* strea
     check_opts(o);
     std::unique_ptr<lp_server> s(new lp_server());
     s->stream.init(stream);
-    // split the budget over the three spaces for a reference mix of
-    // n = 4 m and nnz = 36 m (sizes of the batched workload)
-    const int64_t sz = o.precision == 1 ? 4 : 8;
-    const int64_t per_row = 4 + 24 + 9 * sz, per_col = 4 + 40 + 10 * sz;
-    const int64_t per_nz = 24 + (o.precision == 1 ? 8 : 0);
-    const int64_t unit = per_row + 4 * per_col + 36 * per_nz;
-    const int64_t u = budget / unit;
-    if (u < 16) return fail(LP_ERR_INVALID, "budget too small");
-    const int64_t cap_nz = std::min<int64_t>(36 * u, INT32_MAX - 1);
+    s->opt = o;
+    int64_t cm = 0, cn = 0, cz = 0;
+    if (!server_caps(budget, o.precision, &cm, &cn, &cz)) return fail(LP_ERR_INVALID, "budget too small");
     s->budget = budget;
     s->max_slots = max_slots;
-    s->eng = halp::make_engine(o, s->stream.s, u + max_slots, 4 * u + max_slots, cap_nz, max_slots);
+    s->eng = halp::make_engine(o, s->stream.s, cm + max_slots, cn + max_slots, cz, max_slots);
+    if (o.precision == 1 && o.polish_tol > 0.0) {
+      // the FP64 phase gets the same budget
+      halp::Options o64 = o;
+      o64.precision = 0;
+      if (!server_caps(budget, 0, &cm, &cn, &cz)) return fail(LP_ERR_INVALID, "budget too small");
+      s->eng64 = halp::make_engine(o64, s->stream.s, cm + max_slots, cn + max_slots, cz, max_slots);
+    }
     s->t0 = now_s();
     *out = s.release();
     return LP_OK;
@@ -576,6 +724,8 @@ int lp_server_submit(lp_server* s, const lp_problem* p, double tol, int64_t max_
     r.t_arrival = t_arrival;
     if (s->eng->live() == 0 && !s->eng->fits(r.n, m, nnz))
       return fail(LP_ERR_INVALID, "LP is larger than the server's reserved memory");
+    if (s->eng64 && tol < s->opt.polish_tol && s->eng64->live() == 0 && !s->eng64->fits(r.n, m, nnz))
+      return fail(LP_ERR_INVALID, "LP is larger than the server's reserved memory (FP64 phase)");
     *ticket = r.ticket;
     s->queue.push_back(r.ticket);
     s->reqs.emplace(r.ticket, std::move(r));
@@ -583,39 +733,74 @@ int lp_server_submit(lp_server* s, const lp_problem* p, double tol, int64_t max_
   });
 }
 
+namespace {
+
+void finish_request(lp_server* s, Request& r, halp::EngineBase& eng, int slot, const lp_result& res, double tnow) {
+  r.res = res;
+  r.x.resize(r.n);
+  r.y.resize(r.m_eq + r.m_ineq);
+  eng.solution(slot, r.x.data(), r.y.empty() ? nullptr : r.y.data(), false);
+  r.t_done = tnow;
+  r.done = true;
+  r.slot = r.slot64 = -1;
+  eng.remove({slot});
+  // drop the input copy and the staged candidate
+  std::vector<int32_t>().swap(r.rp);
+  std::vector<int32_t>().swap(r.ci);
+  std::vector<double>().swap(r.val);
+  std::vector<double>().swap(r.px);
+  std::vector<double>().swap(r.py);
+}
+
+// admits the longest prefix of `queue` that fits `eng` (preprocessed together)
+std::vector<std::pair<int64_t, int>> admit(lp_server* s, halp::EngineBase& eng, std::deque<int64_t>& queue) {
+  std::vector<std::pair<int64_t, int>> out;
+  if (queue.empty() || eng.live() >= s->max_slots) return out;
+  std::vector<halp::Problem> ps;
+  for (int64_t t : queue) {
+    if ((int)ps.size() >= s->max_slots - eng.live()) break;
+    ps.push_back(request_problem(s->reqs.at(t)));
+  }
+  std::vector<int> ids = eng.add(ps, false, true);
+  for (size_t k = 0; k < ids.size(); ++k) {
+    out.push_back({queue.front(), ids[k]});
+    queue.pop_front();
+  }
+  return out;
+}
+
+}  // namespace
+
 int lp_server_step(lp_server* s, int chunks, int* n_done) {
   return guarded([&]() -> int {
     if (!s || chunks < 0) return fail(LP_ERR_INVALID, "bad argument");
-    // admission: the longest prefix of the FIFO queue that fits, preprocessed together
-    if (!s->queue.empty() && s->eng->live() < s->max_slots) {
-      std::vector<halp::Problem> ps;
-      for (int64_t t : s->queue) {
-        if ((int)ps.size() >= s->max_slots - s->eng->live()) break;
+    // admission to the first (or only) phase
+    {
+      std::map<std::tuple<double, int64_t, int64_t>, std::vector<int>> by_params;
+      for (auto& [t, id] : admit(s, *s->eng, s->queue)) {
         Request& r = s->reqs.at(t);
-        halp::Problem q;
-        q.n = r.n;
-        q.m_eq = r.m_eq;
-        q.m_ineq = r.m_ineq;
-        q.rp = r.rp.data();
-        q.ci = r.ci.data();
-        q.val = r.val.data();
-        q.c = r.c.data();
-        q.rhs = r.rhs.data();
-        q.lb = r.lb.data();
-        q.ub = r.ub.data();
-        ps.push_back(q);
+        const bool polish = s->eng64 && r.tol < s->opt.polish_tol;
+        by_params[{polish ? s->opt.polish_tol : r.tol, r.max_iter, polish ? s->opt.stall_checks : 0}].push_back(id);
+        r.slot = id;
+        s->slot_ticket[id] = t;
       }
-      std::vector<int> ids = s->eng->add(ps, false, true);
-      std::map<std::pair<double, int64_t>, std::vector<int>> by_params;
-      for (size_t k = 0; k < ids.size(); ++k) {
-        const int64_t t = s->queue.front();
-        s->queue.pop_front();
+      for (auto& kv : by_params)
+        s->eng->set_params(kv.second, std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first));
+    }
+    // admission to the FP64 polish phase, from the FP32 candidates
+    if (s->eng64) {
+      for (auto& [t, id] : admit(s, *s->eng64, s->queue64)) {
         Request& r = s->reqs.at(t);
-        by_params[{r.tol, r.max_iter}].push_back(ids[k]);
-        r.slot = ids[k];
-        s->slot_ticket[ids[k]] = t;
+        double* buf = s->staging(r.n + r.m_eq + r.m_ineq + 1);
+        hip_ok(hipMemcpy(buf, r.px.data(), sizeof(double) * r.n, hipMemcpyHostToDevice), "staging copy");
+        if (!r.py.empty())
+          hip_ok(hipMemcpy(buf + r.n, r.py.data(), sizeof(double) * r.py.size(), hipMemcpyHostToDevice),
+                 "staging copy");
+        s->eng64->import_point(id, buf, buf + r.n, r.pomega);
+        s->eng64->set_params({id}, r.tol, r.max_iter - r.first.iters);
+        r.slot64 = id;
+        s->slot_ticket64[id] = t;
       }
-      for (auto& kv : by_params) s->eng->set_params(kv.second, kv.first.first, kv.first.second);
     }
     int nd = 0;
     if (s->eng->live() > 0 && chunks > 0) {
@@ -624,19 +809,41 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
       for (int slot : done) {
         const int64_t t = s->slot_ticket.at(slot);
         Request& r = s->reqs.at(t);
-        r.res = to_result(s->eng->result(slot), 0.0);
-        r.x.resize(r.n);
-        r.y.resize(r.m_eq + r.m_ineq);
-        s->eng->solution(slot, r.x.data(), r.y.empty() ? nullptr : r.y.data(), false);
-        r.t_done = tnow;
-        r.done = true;
-        r.slot = -1;
         s->slot_ticket.erase(slot);
-        s->eng->remove({slot});
-        // drop the input copy
-        std::vector<int32_t>().swap(r.rp);
-        std::vector<int32_t>().swap(r.ci);
-        std::vector<double>().swap(r.val);
+        const halp::Result res = s->eng->result(slot);
+        if (s->eng64 && r.tol < s->opt.polish_tol && polish_wanted(res, r.max_iter)) {
+          // stage the FP32 candidate on the host and queue the FP64 phase
+          double* buf = s->staging(r.n + r.m_eq + r.m_ineq + 1);
+          s->eng->export_point(slot, buf, buf + r.n, &r.pomega);
+          r.px.resize(r.n);
+          r.py.resize(r.m_eq + r.m_ineq);
+          hip_ok(hipMemcpy(r.px.data(), buf, sizeof(double) * r.n, hipMemcpyDeviceToHost), "staging copy");
+          if (!r.py.empty())
+            hip_ok(hipMemcpy(r.py.data(), buf + r.n, sizeof(double) * r.py.size(), hipMemcpyDeviceToHost),
+                   "staging copy");
+          r.first = res;
+          r.slot = -1;
+          s->eng->remove({slot});
+          s->queue64.push_back(t);
+          continue;
+        }
+        finish_request(s, r, *s->eng, slot, to_result(res, 0.0), tnow);
+        ++nd;
+      }
+    }
+    if (s->eng64 && s->eng64->live() > 0 && chunks > 0) {
+      std::vector<int> done = s->eng64->advance(chunks);
+      const double tnow = s->clock();
+      for (int slot : done) {
+        const int64_t t = s->slot_ticket64.at(slot);
+        Request& r = s->reqs.at(t);
+        s->slot_ticket64.erase(slot);
+        lp_result o = to_result(s->eng64->result(slot), 0.0);
+        o.polish_iters = o.iters;
+        o.iters += r.first.iters;
+        o.restarts += r.first.restarts;
+        o.checks += r.first.checks;
+        finish_request(s, r, *s->eng64, slot, o, tnow);
         ++nd;
       }
     }
@@ -693,13 +900,17 @@ int lp_server_clock(const lp_server* s, double* now) {
 int lp_server_info(const lp_server* s, int* queued, int* live, int64_t* bytes) {
   return guarded([&]() -> int {
     if (!s) return fail(LP_ERR_INVALID, "null handle");
-    if (queued) *queued = (int)s->queue.size();
-    if (live) *live = s->eng->live();
+    if (queued) *queued = (int)(s->queue.size() + s->queue64.size());
+    if (live) *live = s->eng->live() + (s->eng64 ? s->eng64->live() : 0);
     if (bytes) {
       int64_t b = 0;
       for (auto& kv : s->slot_ticket) {
         const Request& r = s->reqs.at(kv.second);
         b += s->eng->footprint(r.n, r.m_eq + r.m_ineq, r.nnz);
+      }
+      for (auto& kv : s->slot_ticket64) {
+        const Request& r = s->reqs.at(kv.second);
+        b += s->eng64->footprint(r.n, r.m_eq + r.m_ineq, r.nnz);
       }
       *bytes = b;
     }

@@ -47,10 +47,13 @@ struct Options {
   int use_graph = 1;
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
   int64_t slice_min_bytes = 2 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
-  double polish_tol = 1e-6;  // fp32: solve to this tolerance in fp32, then polish in fp64
+  double polish_tol = 1e-3;  // fp32: solve to this tolerance in fp32, then polish in fp64
   // bytes of vectors and matrix tiles the step kernels keep in the last-level
   // (Infinity) cache; tiles beyond it are read with non-temporal loads (< 0: all cached)
   int64_t cache_budget_bytes = 208ll << 20;
+  // FP32 phase before an FP64 polish: an LP leaves it after this many checks
+  // without a 10% drop of its best KKT error (its FP32 floor), 0: never
+  int64_t stall_checks = 200;
   int verbose = 0;
 };
 
@@ -59,6 +62,7 @@ struct Options {
 struct KernelTimes {
   double primal_slice_ms = 0.0, primal_ms = 0.0, dual_slice_ms = 0.0, dual_ms = 0.0;
   double event_pair_ms = 0.0;  // two events recorded back to back: included in every figure above
+  double nnz = 0.0, n = 0.0, m = 0.0;  // entries, variables and rows of the LPs in the timed steps (sums)
   int64_t launches = 0;        // timed steps
 };
 
@@ -83,7 +87,11 @@ class EngineBase {
   // add LPs (validated, preprocessed, iterates initialised); returns slot ids.
   // partial: admit the longest prefix that fits instead of failing.
   virtual std::vector<int> add(const std::vector<Problem>& probs, bool on_device, bool partial = false) = 0;
-  virtual void set_params(const std::vector<int>& ids, double tol, int64_t max_iter) = 0;
+  // tolerance and iteration limit of the next solve; stall_checks > 0 also
+  // ends an LP (ITER_LIMIT) after that many checks without a 10% drop of its
+  // best KKT error (a low-precision phase that has reached its floor)
+  virtual void set_params(const std::vector<int>& ids, double tol, int64_t max_iter,
+                          int64_t stall_checks = 0) = 0;
   // run until every listed slot has terminated (or the time limit)
   virtual void run(double time_limit_s) = 0;
   // advance all live slots by `chunks` chunks; returns slots that finished since last call

@@ -260,7 +260,8 @@ class Engine final : public EngineBase {
   }
 
   std::vector<int> add(const std::vector<Problem>& probs, bool on_device, bool partial) override;
-  void set_params(const std::vector<int>& ids, double tol, int64_t max_iter) override;
+  void set_params(const std::vector<int>& ids, double tol, int64_t max_iter,
+                  int64_t stall_checks = 0) override;
   void run(double time_limit_s) override;
   std::vector<int> advance(int chunks) override;
   void remove(const std::vector<int>& ids) override;
@@ -333,6 +334,8 @@ class Engine final : public EngineBase {
   std::vector<hipEvent_t> pev_;  // 6 events per step of one chunk, reused by each timed chunk
   bool pev_pending_ = false;     // pev_ holds a timed chunk not yet added to ktimes_
   bool pev_slices_[2] = {false, false};  // the timed chunk launched primal / dual slice kernels
+  double pev_size_[3] = {0, 0, 0};       // nnz, n, m of the LPs in the timed chunk's schedules
+  double sched_size_[3] = {0, 0, 0};     // the same for the current schedules
   KernelTimes ktimes_;
 };
 
@@ -938,6 +941,9 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
       s.ray = 0;
       s.iters = 0;
       s.kkt = NAN;
+      s.best_kkt = INFINITY;
+      s.best_check = 0;
+      s.stall_checks = 0;
       h_st_[ids[k]] = s;
     }
     HIPCHECK(hipMemcpyAsync(d_src, cur.data(), sizeof(InstState) * ni, hipMemcpyHostToDevice, stream_));
@@ -1027,7 +1033,7 @@ void Engine<T>::slice_matrix(int id, bool dual) {
 }
 
 template <class T>
-void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_iter) {
+void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_iter, int64_t stall_checks) {
   HIPCHECK(hipStreamSynchronize(stream_));
   const int ni = (int)ids.size();
   if (ni == 0) return;
@@ -1039,6 +1045,9 @@ void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_
     InstState& s = cur[k];
     s.tol = tol;
     s.max_iter = max_iter;
+    s.stall_checks = stall_checks;
+    s.best_kkt = INFINITY;
+    s.best_check = s.checks;
     if (s.status != ST_RUNNING) {
       // (re)start from the last candidate as a fresh epoch is not supported
       // for finished LPs; a parked LP starts here
@@ -1126,6 +1135,12 @@ void Engine<T>::rebuild_schedules() {
     live.push_back(s);
     rg.push_back(r);
   }
+  for (double& v : sched_size_) v = 0.0;
+  for (int s : live) {
+    sched_size_[0] += (double)slots_[s].nnz;
+    sched_size_[1] += (double)slots_[s].n;
+    sched_size_[2] += (double)slots_[s].m;
+  }
   mark_streaming(live, P, PS, DS, D);
   HIPCHECK(hipStreamSynchronize(stream_));
   auto upload = [&](std::vector<Blk>& v, Blk*& d, int64_t& cap, int64_t& n, double** part) {
@@ -1208,6 +1223,7 @@ void Engine<T>::launch_chunk() {
     pev_pending_ = true;
     pev_slices_[0] = nPS_ > 0;
     pev_slices_[1] = nDS_ > 0;
+    for (int q = 0; q < 3; ++q) pev_size_[q] = sched_size_[q];
   } else if (opt_.use_graph) {
     if (!gexec_) {
       HIPCHECK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
@@ -1237,6 +1253,9 @@ void Engine<T>::collect_times() {
     if (pev_slices_[1]) ktimes_.dual_slice_ms += d[2];
     ktimes_.dual_ms += d[3];
     ktimes_.event_pair_ms += d[4];
+    ktimes_.nnz += pev_size_[0];
+    ktimes_.n += pev_size_[1];
+    ktimes_.m += pev_size_[2];
     ktimes_.launches += 1;
   }
   pev_pending_ = false;

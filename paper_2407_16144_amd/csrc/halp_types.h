@@ -82,6 +82,11 @@ struct alignas(16) InstState {
   double kkt, rel_p, rel_d, rel_gap, pobj, dobj, resid;
   int64_t iters;
   int32_t ray, pad0;
+  // stall rule (a low-precision phase ends when its KKT error stops falling):
+  // best error so far, the check that set it, and the allowed checks without
+  // a 10% improvement (0: off)
+  double best_kkt;
+  int64_t best_check, stall_checks;
   // power iteration
   double pw_scale, pw_prev, sigma_hat;
   int32_t pw_iter, pw_done;

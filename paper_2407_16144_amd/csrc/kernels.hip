@@ -530,6 +530,11 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
       }
     }
     if (st == ST_RUNNING && t >= S.max_iter) st = ST_ITER_LIMIT;
+    if (!(kkt >= 0.9 * S.best_kkt)) {
+      S.best_kkt = kkt;
+      S.best_check = S.checks;
+    }
+    if (st == ST_RUNNING && S.stall_checks > 0 && S.checks - S.best_check >= S.stall_checks) st = ST_ITER_LIMIT;
   }
   if (st != ST_RUNNING) {
     S.status = st;

@@ -253,10 +253,51 @@ def test_streamed_tiles_give_identical_iterates(sliced, budget):
 def test_fp32_mode_reaches_moderate_accuracy():
     lp = lpgen.tiny()
     print("case fp32", flush=True)
-    res, x, y, _ = _gpu(lp, 1e-4, 200_000, precision=halp.LP_PREC_FP32)
-    assert res["status"] == halp.LP_OPTIMAL
+    res, x, y, _ = _gpu(lp, 1e-4, 200_000, precision=halp.LP_PREC_FP32, polish_tol=0.0)
+    assert res["status"] == halp.LP_OPTIMAL and res["polish_iters"] == 0
     kkt, parts = oracle.rel_kkt(lp, x, y)
     assert kkt <= 2e-4, parts
+
+
+def test_fp32_stall_rule_hands_over_to_fp64():
+    """An FP32 phase asked for a tolerance below FP32's reach stops at the
+    stall rule, and the FP64 phase finishes the solve."""
+    lp = lpgen.tiny(4)
+    print("case fp32 stall", flush=True)
+    res, x, y, _ = _gpu(lp, 1e-9, 500_000, precision=halp.LP_PREC_FP32, polish_tol=1e-12, stall_checks=20)
+    assert res["status"] == halp.LP_OPTIMAL
+    assert 0 < res["polish_iters"] < res["iters"]
+    kkt, parts = oracle.rel_kkt(lp, x, y)
+    assert kkt <= 1e-9 * (1 + 1e-6), parts
+
+
+def test_batch_fp32_polish():
+    """FP32 batch to the polish tolerance, then FP64 for each LP: statuses
+    equal the FP64 batch's, KKT errors (recomputed by the oracle) within the
+    request, certificates valid."""
+    lps = [lpgen.scaled_powerlaw(400 + i, m, 3 * m) for i, m in enumerate([60, 300, 20, 150])]
+    lps.append(lpgen.add_contradictory_rows(lpgen.scaled_powerlaw(410, 80, 240), seed=3, rel_gap=0.1))
+    print("case batch fp32 polish", flush=True)
+    out = {}
+    for prec in (halp.LP_PREC_FP64, halp.LP_PREC_FP32):
+        h = halp.lp_batch_create(lps, opt=halp.lp_default_options(precision=prec))
+        try:
+            halp.lp_batch_solve(h, 1e-6, 300_000)
+            out[prec] = [(halp.lp_batch_status(h, i).as_dict(), halp.lp_batch_get_solution(h, i, lp.n, lp.m),
+                          halp.lp_batch_get_certificate(h, i, lp.m) if i == len(lps) - 1 else None)
+                         for i, lp in enumerate(lps)]
+        finally:
+            halp.lp_batch_destroy(h)
+    for i, lp in enumerate(lps):
+        r64, r32 = out[halp.LP_PREC_FP64][i][0], out[halp.LP_PREC_FP32][i][0]
+        assert r32["status"] == r64["status"]
+        if r32["status"] == halp.LP_OPTIMAL:
+            assert r32["polish_iters"] > 0
+            x, y = out[halp.LP_PREC_FP32][i][1]
+            kkt, parts = oracle.rel_kkt(lp, x, y)
+            assert kkt <= 1e-6 * (1 + 1e-6), parts
+    assert out[halp.LP_PREC_FP32][-1][0]["status"] == halp.LP_PRIMAL_INFEASIBLE
+    assert oracle.primal_ray_check(lps[-1], out[halp.LP_PREC_FP32][-1][2])[0]
 
 
 def test_iteration_limit_and_errors():
@@ -362,14 +403,18 @@ def test_fp32_with_fp64_polish(on_device):
     assert abs(res["pobj"] - ref.pobj) <= 1e-8 * (1 + abs(ref.pobj))
 
 
-def test_server_results_equal_single_results():
+@pytest.mark.parametrize("prec", [halp.LP_PREC_FP64, halp.LP_PREC_FP32])
+def test_server_results_equal_single_results(prec):
     """Continuous batching: LPs submitted at different times, admitted as
-    memory frees up, give the same result as solving each alone."""
+    memory frees up, give the same result as solving each alone.  FP32: each
+    LP's FP32 phase and its FP64 polish phase run in the server's two
+    engines, and still match the single solve bit for bit."""
     lps = [lpgen.scaled_powerlaw(400 + i, m, 3 * m) for i, m in enumerate([50, 400, 120, 900, 30, 250])]
     lps.append(lpgen.add_contradictory_rows(lpgen.tiny(8), seed=3))
     lps.append(lpgen.add_unbounded_column(lpgen.scaled_powerlaw(6, 40, 120), seed=2))
-    print("case server", flush=True)
-    opt = halp.lp_default_options(use_graph=0)
+    print(f"case server precision={prec}", flush=True)
+    opt = halp.lp_default_options(use_graph=0, precision=prec)
+    phases = 2 if prec == halp.LP_PREC_FP32 else 1
     # a budget that holds only a few of these at once, and 3 slots
     h = halp.lp_server_create(40_000_000, 3, opt=opt)
     try:
@@ -384,7 +429,7 @@ def test_server_results_equal_single_results():
                 break
             halp.lp_server_step(h, 4)
             q, live, used = halp.lp_server_info(h)
-            assert live <= 3
+            assert live <= 3 * phases
             for t in list(pending):
                 r, td = halp.lp_server_poll(h, t)
                 if r is not None:
@@ -397,7 +442,12 @@ def test_server_results_equal_single_results():
     finally:
         halp.lp_server_destroy(h)
     for k, lp in enumerate(lps):
-        rs, xs, ys, _ = _gpu(lp, 1e-6, 200_000, use_graph=0)
+        rs, xs, ys, _ = _gpu(lp, 1e-6, 200_000, use_graph=0, precision=prec)
         rb, xb, yb = res[k]
         assert rb["status"] == rs["status"] and rb["iters"] == rs["iters"], (k, rb, rs)
+        assert rb["polish_iters"] == rs["polish_iters"], k
         assert np.array_equal(xb, xs) and np.array_equal(yb, ys), k
+        if prec == halp.LP_PREC_FP32 and rb["status"] == halp.LP_OPTIMAL:
+            assert rb["polish_iters"] > 0
+            kkt, parts = oracle.rel_kkt(lp, xb, yb)
+            assert kkt <= 1e-6 * (1 + 1e-6), parts
