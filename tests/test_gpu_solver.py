@@ -264,11 +264,13 @@ def test_fp32_stall_rule_hands_over_to_fp64():
     stall rule, and the FP64 phase finishes the solve."""
     lp = lpgen.tiny(4)
     print("case fp32 stall", flush=True)
-    res, x, y, _ = _gpu(lp, 1e-9, 500_000, precision=halp.LP_PREC_FP32, polish_tol=1e-12, stall_checks=20)
-    assert res["status"] == halp.LP_OPTIMAL
-    assert 0 < res["polish_iters"] < res["iters"]
+    # an FP32 phase cannot reach a 1e-9 relative KKT error: without the stall
+    # rule it would spend the whole iteration budget and leave no polish
+    res, x, y, _ = _gpu(lp, 5e-10, 500_000, precision=halp.LP_PREC_FP32, polish_tol=1e-9, stall_checks=20)
+    assert res["status"] == halp.LP_OPTIMAL, res
+    assert 0 < res["polish_iters"] < res["iters"] < 250_000, res
     kkt, parts = oracle.rel_kkt(lp, x, y)
-    assert kkt <= 1e-9 * (1 + 1e-6), parts
+    assert kkt <= 5e-10 * (1 + 1e-6), parts
 
 
 def test_batch_fp32_polish():
