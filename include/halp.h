@@ -71,6 +71,12 @@ typedef enum {
 typedef enum { LP_METHOD_RHPDHG = 0, LP_METHOD_R2HPDHG = 1 } lp_method;
 typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32 = 1 } lp_precision;
 
+typedef enum {
+  LP_RESTART_ADAPTIVE = 0,
+  LP_RESTART_FIXED = 1,
+  LP_RESTART_NONE = 2
+} lp_restart_mode;
+
 typedef struct {
   int method;               /* lp_method; default r2HPDHG (Algorithm 2) */
   int precision;            /* lp_precision; FP32 stores K, K^T and the iterate
@@ -110,6 +116,11 @@ typedef struct {
   int64_t stall_checks;     /* FP32 phase of a polished solve: an LP moves on to the FP64
                                phase after this many checks without a 10% drop of its
                                best relative KKT error (default 200; 0: only at polish_tol) */
+  int restart_mode;         /* lp_restart_mode: LP_RESTART_ADAPTIVE (default; eq.
+                               (adaptive-restart) plus the artificial rule),
+                               LP_RESTART_FIXED (eq. (fixed-restart): at the first check
+                               with k >= fixed_restart_len), LP_RESTART_NONE */
+  int64_t fixed_restart_len; /* k* of LP_RESTART_FIXED (>= 1) */
 } lp_options;
 
 typedef struct {

@@ -319,7 +319,8 @@ def solve(lp, opts: Options | None = None) -> Result:
                 entry["restart"] = True
                 dxn = float(np.linalg.norm(xp - x0))
                 dyn = float(np.linalg.norm(yp - y0))
-                if opts.primal_weight and dxn > 1e-10 and dyn > 1e-10:
+                if (opts.primal_weight and dxn > 1e-10 and dyn > 1e-10
+                        and math.isfinite(dxn) and math.isfinite(dyn)):
                     omega = math.exp(0.5 * math.log(dyn / dxn) + 0.5 * math.log(omega))
                 tau, sigma = eta / omega, eta * omega
                 x0, y0 = xp.copy(), yp.copy()

@@ -32,6 +32,7 @@ STATUS_NAMES = {0: "UNSOLVED", 1: "OPTIMAL", 2: "PRIMAL_INFEASIBLE", 3: "DUAL_IN
                 4: "ITER_LIMIT", 5: "TIME_LIMIT", 6: "NUMERICAL"}
 LP_METHOD_RHPDHG, LP_METHOD_R2HPDHG = 0, 1
 LP_PREC_FP64, LP_PREC_FP32 = 0, 1
+LP_RESTART_ADAPTIVE, LP_RESTART_FIXED, LP_RESTART_NONE = 0, 1, 2
 
 
 class lp_options(C.Structure):
@@ -43,7 +44,8 @@ class lp_options(C.Structure):
                 ("primal_weight", C.c_int), ("seed", C.c_uint64), ("eta", C.c_double),
                 ("omega0", C.c_double), ("chunk", C.c_int), ("use_graph", C.c_int),
                 ("profile", C.c_int), ("slice_min_bytes", C.c_int64), ("polish_tol", C.c_double),
-                ("verbose", C.c_int), ("cache_budget_bytes", C.c_int64), ("stall_checks", C.c_int64)]
+                ("verbose", C.c_int), ("cache_budget_bytes", C.c_int64), ("stall_checks", C.c_int64),
+                ("restart_mode", C.c_int), ("fixed_restart_len", C.c_int64)]
 
 
 class lp_result(C.Structure):

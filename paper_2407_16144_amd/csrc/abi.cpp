@@ -64,10 +64,15 @@ halp::Options to_opts(const lp_options* o) {
   r.verbose = o->verbose;
   r.cache_budget_bytes = o->cache_budget_bytes;
   r.stall_checks = o->stall_checks;
+  r.restart_mode = o->restart_mode;
+  r.fixed_restart_len = o->fixed_restart_len;
   return r;
 }
 
 void check_opts(const halp::Options& o) {
+  if (o.restart_mode < 0 || o.restart_mode > 2) throw halp::Error(LP_ERR_INVALID, "restart_mode must be 0, 1 or 2");
+  if (o.restart_mode == 1 && o.fixed_restart_len < 1)
+    throw halp::Error(LP_ERR_INVALID, "fixed restarts need fixed_restart_len >= 1");
   if (o.method != 0 && o.method != 1) throw halp::Error(LP_ERR_INVALID, "method must be 0 or 1");
   if (o.precision != 0 && o.precision != 1) throw halp::Error(LP_ERR_INVALID, "precision must be 0 or 1");
   if (o.check_every < 1 || o.chunk < 1 || o.chunk > 4096)
@@ -366,6 +371,8 @@ void lp_default_options(lp_options* o) {
   o->verbose = d.verbose;
   o->cache_budget_bytes = d.cache_budget_bytes;
   o->stall_checks = d.stall_checks;
+  o->restart_mode = d.restart_mode;
+  o->fixed_restart_len = d.fixed_restart_len;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }

@@ -932,6 +932,8 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
       s.primal_weight = opt_.primal_weight;
       s.beta = opt_.restart_beta;
       s.artificial = opt_.artificial_restart;
+      s.restart_mode = opt_.restart_mode;
+      s.fixed_len = opt_.fixed_restart_len;
       s.eps_inf = opt_.eps_infeas;
       s.r0 = NAN;
       s.status = ST_ITER_LIMIT;  // parked

@@ -87,6 +87,10 @@ struct alignas(16) InstState {
   // a 10% improvement (0: off)
   double best_kkt;
   int64_t best_check, stall_checks;
+  // restart rule: 0 adaptive (eq. (adaptive-restart) + artificial), 1 fixed
+  // frequency (eq. (fixed-restart), k >= fixed_len), 2 none
+  int64_t fixed_len;
+  int32_t restart_mode, pad1;
   // power iteration
   double pw_scale, pw_prev, sigma_hat;
   int32_t pw_iter, pw_done;

@@ -542,11 +542,14 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
     status_out[inst] = st;
     return;
   }
-  const bool restart = (S.nrest == 0) || (res <= S.beta * S.r0) ||
-                       (S.artificial > 0.0 && (double)k >= S.artificial * (double)t);
+  bool restart = false;
+  if (S.restart_mode == 0)
+    restart = (S.nrest == 0) || (res <= S.beta * S.r0) || (S.artificial > 0.0 && (double)k >= S.artificial * (double)t);
+  else if (S.restart_mode == 1)
+    restart = k >= S.fixed_len;
   if (restart) {
     const double dX = sqrt(S.acc[A_AX2]), dY = sqrt(S.acc[A_AY2]);
-    if (S.primal_weight && dX > 1e-10 && dY > 1e-10)
+    if (S.primal_weight && dX > 1e-10 && dY > 1e-10 && isfinite(dX) && isfinite(dY))
       S.omega = exp(0.5 * log(dY / dX) + 0.5 * log(S.omega));
     S.tau = S.eta / S.omega;
     S.sigma = S.eta * S.omega;

@@ -51,6 +51,15 @@ def test_struct_layouts_match_header():
     assert fields("lp_kernel_timing") == [f for f, _ in halp.lp_kernel_timing._fields_]
 
 
+def test_enum_values_match_header():
+    src = open(HEADER).read()
+    for name in ["LP_RESTART_ADAPTIVE", "LP_RESTART_FIXED", "LP_RESTART_NONE", "LP_OPTIMAL",
+                 "LP_PRIMAL_INFEASIBLE", "LP_DUAL_INFEASIBLE", "LP_ITER_LIMIT"]:
+        m = re.search(name + r"\s*=\s*(\d+)", src)
+        assert m, name
+        assert int(m.group(1)) == getattr(halp, name), name
+
+
 def test_default_options():
     o = halp.lp_default_options()
     assert o.method == halp.LP_METHOD_R2HPDHG and o.precision == halp.LP_PREC_FP64
@@ -91,7 +100,8 @@ def test_invalid_lp_rejected_on_host(mutate, needle):
 
 def test_invalid_options_rejected():
     a = _tiny_arrays()
-    for kw in [dict(method=3), dict(precision=2), dict(check_every=0), dict(step_safety=0.0)]:
+    for kw in [dict(method=3), dict(precision=2), dict(check_every=0), dict(step_safety=0.0),
+               dict(restart_mode=3), dict(restart_mode=halp.LP_RESTART_FIXED, fixed_restart_len=0)]:
         with pytest.raises(halp.HalpError) as ei:
             halp.lp_create(a["n"], a["m_eq"], a["m_ineq"], a["row_ptr"], a["col_idx"], a["val"],
                            a["c"], a["rhs"], a["lb"], a["ub"], opt=halp.lp_default_options(**kw))

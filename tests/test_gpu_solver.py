@@ -233,6 +233,38 @@ def test_graph_and_stream_launch_agree(graph):
 
 
 
+
+@pytest.mark.parametrize("name,code", METHODS)
+@pytest.mark.parametrize("mode,kstar", [("fixed", 150), ("fixed", 64), ("none", 0)])
+def test_restart_rules_trajectory_parity(name, code, mode, kstar):
+    """eq. (fixed-restart) and no restarts: the same iterates as the oracle."""
+    lp = lpgen.scaled_powerlaw(23, 300, 1000)
+    print(f"case restart {mode} k*={kstar} {name}", flush=True)
+    rm = halp.LP_RESTART_FIXED if mode == "fixed" else halp.LP_RESTART_NONE
+    res, x, y, _ = _gpu(lp, 0.0, 1000, method=code, restart_mode=rm, fixed_restart_len=max(kstar, 1))
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=0.0, max_iter=1000, restart=mode,
+                                          fixed_restart_len=kstar))
+    assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
+    assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
+
+
+@pytest.mark.parametrize("name,code", METHODS)
+def test_fixed_restart_certificates(name, code):
+    """The infeasibility regime of Section 5 (fixed-frequency restarts): a
+    primal-infeasible LP is certified at the same check as by the oracle,
+    and the ray passes the oracle's Farkas test.  (On the planted unbounded
+    LP, fixed restarts do not reach the 1e-8 dual-ray test within 400k
+    iterations on either side; adaptive restarts do.)"""
+    lp = lpgen.add_contradictory_rows(lpgen.tiny(7), seed=4)
+    print(f"case fixed-restart primal infeasible {name}", flush=True)
+    opt = dict(method=code, restart_mode=halp.LP_RESTART_FIXED, fixed_restart_len=256)
+    res, x, y, ray = _gpu(lp, 1e-8, 200_000, **opt)
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=1e-8, max_iter=200_000, restart="fixed",
+                                          fixed_restart_len=256))
+    assert res["status"] == ref.status == halp.LP_PRIMAL_INFEASIBLE
+    assert res["iters"] == ref.iters
+    assert oracle.primal_ray_check(lp, ray)[0]
+
 @pytest.mark.parametrize("sliced,budget", [(False, 0), (True, 0), (False, 150_000), (True, 330_000)])
 def test_streamed_tiles_give_identical_iterates(sliced, budget):
     """Matrix tiles past the cache budget are read with non-temporal loads:

@@ -309,6 +309,35 @@ def test_fejer_monotone_restart_points():
         assert all(b <= a * (1 + 1e-10) + 1e-13 for a, b in zip(anchors, anchors[1:]))
 
 
+
+@pytest.mark.parametrize("kstar", [64, 150])
+def test_fixed_frequency_restarts(kstar):
+    """eq. (fixed-restart): with checks every 64 steps, every epoch ends at
+    the first check with k >= k*; Lemma iterates-feas holds for this rule
+    too: with a fixed norm the restart points approach z* monotonically."""
+    lp = lpgen.planted_opt(8, m_eq=12, m_ineq=8, n=30)
+    anchors = []
+
+    def cb(s):
+        if s["k"] == 0:
+            P = s["P"]
+            xs, ys = lp.meta["x_opt"] / P.Dc, lp.meta["y_opt"] / P.Dr
+            anchors.append(oracle.m_norm(P, s["x0"] - xs, s["y0"] - ys, s["tau"], s["sigma"]))
+
+    r = oracle.solve(lp, oracle.Options(restart="fixed", fixed_restart_len=kstar, primal_weight=False,
+                                        tol=1e-9, callback=cb))
+    assert r.status == core.OPTIMAL
+    ks = [e["k"] for e in r.log if e["restart"]]
+    first_check = -(-kstar // 64) * 64
+    assert len(ks) >= 2 and all(k == first_check for k in ks)
+    assert all(b <= a * (1 + 1e-10) + 1e-13 for a, b in zip(anchors, anchors[1:]))
+
+
+def test_no_restarts():
+    lp = lpgen.tiny()
+    r = oracle.solve(lp, oracle.Options(restart="none", tol=0.0, max_iter=2000))
+    assert r.restarts == 0 and not any(e["restart"] for e in r.log)
+
 # ---------------------------------------------------------------- whole solves
 
 def test_one_dimensional_example_limit():
