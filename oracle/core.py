@@ -174,7 +174,7 @@ def halpern_point(xp, yp, x, y, x0, y0, k, reflect):
 
 @dataclass
 class Options:
-    method: str = "r2hpdhg"          # "rhpdhg" (Algorithm 1) or "r2hpdhg" (Algorithm 2)
+    method: str = "r2hpdhg"          # "rhpdhg" (Algorithm 1), "r2hpdhg" (Algorithm 2) or "rapdhg"
     tol: float = 1e-8                # relative KKT tolerance
     max_iter: int = 1_000_000        # enforced at check points: stop at the first check with t >= max_iter
     ruiz_iters: int = 10
@@ -183,6 +183,8 @@ class Options:
     restart: str = "adaptive"        # "adaptive" (eq. (adaptive-restart)), "fixed", "none"
     fixed_restart_len: int = 0       # k* for restart == "fixed" (eq. (fixed-restart))
     restart_beta: float = math.exp(-1.0)
+    avg_beta_sufficient: float = 0.2  # rapdhg: KKT-based restart thresholds (cuPDLP's values)
+    avg_beta_necessary: float = 0.8
     artificial_restart: float = 0.36  # also restart when k >= this * t (0 disables)
     step_safety: float = 0.9
     power_max_iters: int = 1000
@@ -278,6 +280,9 @@ def solve(lp, opts: Options | None = None) -> Result:
         return Result(status, xu, yu, t, nrest, kkt, parts["pobj"], parts["dobj"], parts,
                       omega, eta, sigma_hat, piters, ray, log, P)
 
+    if opts.method == "rapdhg":
+        return _solve_average(lp, opts, P, K0, eta, sigma_hat, piters, omega, x, y)
+
     while True:
         xp, yp = pdhg_T(P, x, y, tau, sigma)
         t += 1
@@ -329,4 +334,99 @@ def solve(lp, opts: Options | None = None) -> Result:
                 k = 0
                 continue
         x, y = halpern_point(xp, yp, x, y, x0, y0, k, reflect)
+        k += 1
+
+
+def _solve_average(lp, opts, P, K0, eta, sigma_hat, piters, omega, x, y) -> Result:
+    """Restarted average PDHG (raPDHG, the base algorithm of PDLP/cuPDLP that
+    the paper compares with, Section 2 and Section 7).  The paper describes it
+    only as: run vanilla PDHG (eq. (pdhg)) within an epoch and restart at the
+    average of the epoch's iterates, with cuPDLP's KKT-based adaptive restart.
+    Readings:
+      * average (as in Proposition 1): zbar^{n,k} = (1/(k+1)) sum_{i=0}^{k}
+        z^{n,i}, the epoch's start included; at the check after the T
+        evaluation of inner step k the candidate is zbar^{n,k+1};
+      * checks at k > 0, k % C == 0 as for rHPDHG; termination and the
+        iteration limit are tested at the candidate, the infeasibility tests on
+        the same rays as rHPDHG (T(z) - z and z - z^{n,0}, z the current
+        vanilla iterate);
+      * restart metric: the relative KKT error at the candidate.  The first
+        epoch restarts at its first check; later epochs restart when
+        KKT(cand) <= 0.2 KKT(z^{n,0}), or KKT(cand) <= 0.8 KKT(z^{n,0}) and
+        KKT(cand) > KKT at the epoch's previous check, or k >= 0.36 t
+        (cuPDLP's sufficient / necessary + no-progress / artificial rules);
+        restart_mode "fixed" and "none" as for rHPDHG;
+      * restart point: the candidate (the average); primal weight update as
+        for rHPDHG with the distance between consecutive restart points."""
+    tau, sigma = eta / omega, eta * omega
+    x0, y0 = x.copy(), y.copy()
+    sx, sy = x.copy(), y.copy()      # sums of the epoch's iterates z^{n,0..k}
+    cnt = 1
+    nrest, k, t = 0, 0, 0
+    kkt_anchor, kkt_prev = float("nan"), float("inf")
+    C = opts.check_every
+    log = []
+
+    def finish(status, xc, yc, ray=None):
+        xu, yu = P.Dc * xc, P.Dr * yc
+        kkt, parts = rel_kkt(lp, xu, yu, K0)
+        return Result(status, xu, yu, t, nrest, kkt, parts["pobj"], parts["dobj"], parts,
+                      omega, eta, sigma_hat, piters, ray, log, P)
+
+    while True:
+        xp, yp = pdhg_T(P, x, y, tau, sigma)
+        t += 1
+        sx = sx + xp
+        sy = sy + yp
+        cnt += 1
+        if opts.callback is not None:
+            opts.callback(dict(t=t, n=nrest, k=k, x=x, y=y, xp=xp, yp=yp, x0=x0, y0=y0,
+                               xa=sx / cnt, ya=sy / cnt, tau=tau, sigma=sigma, P=P))
+        if k > 0 and k % C == 0:
+            xa, ya = sx / cnt, sy / cnt
+            kkt, parts = rel_kkt(lp, P.Dc * xa, P.Dr * ya, K0)
+            entry = dict(t=t, n=nrest, k=k, kkt=kkt, kkt_anchor=kkt_anchor, kkt_prev=kkt_prev,
+                         restart=False)
+            log.append(entry)
+            if not np.isfinite(kkt):
+                return finish(NUMERICAL, xa, ya)
+            if kkt <= opts.tol:
+                return finish(OPTIMAL, xa, ya)
+            cands = [(xp - x, yp - y), (x - x0, y - y0)]
+            for _, dy in cands:
+                ok, info = primal_ray_check(lp, P.Dr * dy, opts.eps_infeas, K0)
+                if ok:
+                    return finish(PRIMAL_INFEASIBLE, xa, ya, info["ray"])
+            for dx, _ in cands:
+                ok, info = dual_ray_check(lp, P.Dc * dx, opts.eps_infeas, K0)
+                if ok:
+                    return finish(DUAL_INFEASIBLE, xa, ya, info["ray"])
+            if t >= opts.max_iter:
+                return finish(ITER_LIMIT, xa, ya)
+            if opts.restart == "adaptive":
+                do_restart = ((nrest == 0) or (kkt <= opts.avg_beta_sufficient * kkt_anchor)
+                              or (kkt <= opts.avg_beta_necessary * kkt_anchor and kkt > kkt_prev)
+                              or (opts.artificial_restart > 0 and k >= opts.artificial_restart * t))
+            elif opts.restart == "fixed":
+                do_restart = k >= opts.fixed_restart_len
+            else:
+                do_restart = False
+            kkt_prev = kkt
+            if do_restart:
+                entry["restart"] = True
+                dxn = float(np.linalg.norm(xa - x0))
+                dyn = float(np.linalg.norm(ya - y0))
+                if (opts.primal_weight and dxn > 1e-10 and dyn > 1e-10
+                        and math.isfinite(dxn) and math.isfinite(dyn)):
+                    omega = math.exp(0.5 * math.log(dyn / dxn) + 0.5 * math.log(omega))
+                tau, sigma = eta / omega, eta * omega
+                x0, y0 = xa.copy(), ya.copy()
+                x, y = xa, ya
+                sx, sy = xa.copy(), ya.copy()
+                cnt = 1
+                kkt_anchor, kkt_prev = kkt, float("inf")
+                nrest += 1
+                k = 0
+                continue
+        x, y = xp, yp
         k += 1

@@ -338,6 +338,46 @@ def test_no_restarts():
     r = oracle.solve(lp, oracle.Options(restart="none", tol=0.0, max_iter=2000))
     assert r.restarts == 0 and not any(e["restart"] for e in r.log)
 
+
+def test_average_pdhg_average_is_halpern_iterate_on_affine_problem():
+    """Proposition 1 for the raPDHG oracle itself: on the unconstrained
+    bilinear problem, with one step size and no restarts, its running average
+    zbar^{k+1} (epoch start included) is the rHPDHG iterate z^{k+1}."""
+    lp = lpgen.affine(3)
+    P = core.scaled_problem(lp)
+    s, _ = oracle.power_iteration(P.K, 0)
+    opt = dict(eta=0.8 / s, primal_weight=False, restart="none", tol=0.0, max_iter=200)
+    ra, hal = {}, {}
+    oracle.solve(lp, oracle.Options(method="rapdhg", callback=lambda d: ra.__setitem__(d["t"], (d["xa"], d["ya"])),
+                                    **opt))
+    oracle.solve(lp, oracle.Options(method="rhpdhg", callback=lambda d: hal.__setitem__(d["t"], (d["x"], d["y"])),
+                                    **opt))
+    assert len(ra) >= 200
+    for t in range(1, 200):
+        (ax, ay), (hx, hy) = ra[t], hal[t + 1]
+        scale = 1 + np.abs(ax).max() + np.abs(ay).max()
+        assert np.abs(ax - hx).max() <= 1e-12 * scale
+        assert np.abs(ay - hy).max() <= 1e-12 * scale
+
+
+def test_average_pdhg_restart_rule():
+    """raPDHG restarts only at checks, at the first check of the first epoch,
+    and afterwards only when the KKT-based rule holds for the logged values;
+    every epoch without a restart at a check fails all three tests."""
+    lp = lpgen.scaled_powerlaw(23, 300, 1000)
+    r = oracle.solve(lp, oracle.Options(method="rapdhg", tol=1e-6, max_iter=200_000))
+    assert r.status == core.OPTIMAL and r.restarts >= 3
+    first = True
+    for e in r.log[:-1]:           # the last check ended the solve before any restart test
+        if e["n"] == 0:
+            assert e["restart"] == first
+            first = False
+            continue
+        rule = (e["kkt"] <= 0.2 * e["kkt_anchor"]
+                or (e["kkt"] <= 0.8 * e["kkt_anchor"] and e["kkt"] > e["kkt_prev"])
+                or e["k"] >= 0.36 * e["t"])
+        assert e["restart"] == rule
+
 # ---------------------------------------------------------------- whole solves
 
 def test_one_dimensional_example_limit():
@@ -359,14 +399,14 @@ def test_tiny_copy_matches_brute_force(seed):
         assert res.status == 2
         return
     assert res.fun == pytest.approx(best, rel=1e-9, abs=1e-9)
-    for method in ["rhpdhg", "r2hpdhg"]:
+    for method in ["rhpdhg", "r2hpdhg", "rapdhg"]:
         r = oracle.solve(lp, oracle.Options(method=method, tol=1e-9))
         assert r.status == core.OPTIMAL
         assert r.kkt <= 1e-9
         assert abs(r.pobj - best) <= 1e-7 * (1 + abs(best))
 
 
-@pytest.mark.parametrize("method", ["rhpdhg", "r2hpdhg"])
+@pytest.mark.parametrize("method", ["rhpdhg", "r2hpdhg", "rapdhg"])
 def test_tiny_matches_highs(method):
     lp = lpgen.tiny()
     res = _highs(lp)
@@ -405,7 +445,7 @@ def _farkas_primal_dense(lp, y):
 def test_primal_infeasible_certificate():
     lp = lpgen.add_contradictory_rows(lpgen.tiny(5), seed=1)
     assert _highs(lp).status == 2
-    for method in ["rhpdhg", "r2hpdhg"]:
+    for method in ["rhpdhg", "r2hpdhg", "rapdhg"]:
         r = oracle.solve(lp, oracle.Options(method=method, tol=1e-8, max_iter=200_000))
         assert r.status == core.PRIMAL_INFEASIBLE, oracle.STATUS_NAMES[r.status]
         assert _farkas_primal_dense(lp, r.ray)
@@ -425,7 +465,7 @@ def test_dual_infeasible_certificate():
     e = np.zeros(lp.n)
     e[j] = 1.0
     assert oracle.dual_ray_check(lp, e)[0]
-    for method in ["rhpdhg", "r2hpdhg"]:
+    for method in ["rhpdhg", "r2hpdhg", "rapdhg"]:
         r = oracle.solve(lp, oracle.Options(method=method, tol=1e-8, max_iter=200_000))
         assert r.status == core.DUAL_INFEASIBLE, oracle.STATUS_NAMES[r.status]
         d = r.ray
