@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METHODS = {"rhpdhg": 0, "r2hpdhg": 1, "rapdhg": 2}
 
 
 def algorithmic_bytes(n, m, nnz, s):
@@ -118,7 +119,7 @@ def cpu_baseline(lp, eta, gpu_iters, gpu_power_iters, method, budget_s=30.0):
 
 def _opts(halp, args, **kw):
     return halp.lp_default_options(
-        method=halp.LP_METHOD_R2HPDHG if args.method == "r2hpdhg" else halp.LP_METHOD_RHPDHG,
+        method=METHODS[args.method],
         precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64, **kw)
 
 
@@ -282,7 +283,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--method", default="r2hpdhg", choices=["rhpdhg", "r2hpdhg"])
+    ap.add_argument("--method", default="r2hpdhg", choices=list(METHODS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
@@ -336,7 +337,7 @@ def main():
             T(lp.ub, torch.float64))
     stream = torch.cuda.current_stream()
     opt = halp.lp_default_options(
-        method=halp.LP_METHOD_R2HPDHG if args.method == "r2hpdhg" else halp.LP_METHOD_RHPDHG,
+        method=METHODS[args.method],
         precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64,
         profile=args.profile_every, verbose=args.verbose, use_graph=0 if args.no_graph else 1,
         **({} if args.cache_budget_mb is None else {"cache_budget_bytes": int(args.cache_budget_mb * 2**20)}))

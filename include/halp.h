@@ -68,7 +68,11 @@ typedef enum {
   LP_NUMERICAL = 6           /* NaN or Inf in a reduction */
 } lp_status_code;
 
-typedef enum { LP_METHOD_RHPDHG = 0, LP_METHOD_R2HPDHG = 1 } lp_method;
+/* LP_METHOD_RAPDHG: restarted average PDHG, the base method of PDLP / cuPDLP
+ * that the paper compares with (Sections 2 and 7): plain PDHG steps within
+ * an epoch, candidates and restart points at the epoch's running average
+ * (the average of Proposition 1), restarts on cuPDLP's KKT-based rule. */
+typedef enum { LP_METHOD_RHPDHG = 0, LP_METHOD_R2HPDHG = 1, LP_METHOD_RAPDHG = 2 } lp_method;
 typedef enum { LP_PREC_FP64 = 0, LP_PREC_FP32 = 1 } lp_precision;
 
 typedef enum {

@@ -30,7 +30,7 @@ LP_OK, LP_ERR_INVALID, LP_ERR_OOM, LP_ERR_DEVICE, LP_ERR_STATE = 0, -1, -2, -3, 
  LP_TIME_LIMIT, LP_NUMERICAL) = range(7)
 STATUS_NAMES = {0: "UNSOLVED", 1: "OPTIMAL", 2: "PRIMAL_INFEASIBLE", 3: "DUAL_INFEASIBLE",
                 4: "ITER_LIMIT", 5: "TIME_LIMIT", 6: "NUMERICAL"}
-LP_METHOD_RHPDHG, LP_METHOD_R2HPDHG = 0, 1
+LP_METHOD_RHPDHG, LP_METHOD_R2HPDHG, LP_METHOD_RAPDHG = 0, 1, 2
 LP_PREC_FP64, LP_PREC_FP32 = 0, 1
 LP_RESTART_ADAPTIVE, LP_RESTART_FIXED, LP_RESTART_NONE = 0, 1, 2
 

@@ -73,7 +73,7 @@ void check_opts(const halp::Options& o) {
   if (o.restart_mode < 0 || o.restart_mode > 2) throw halp::Error(LP_ERR_INVALID, "restart_mode must be 0, 1 or 2");
   if (o.restart_mode == 1 && o.fixed_restart_len < 1)
     throw halp::Error(LP_ERR_INVALID, "fixed restarts need fixed_restart_len >= 1");
-  if (o.method != 0 && o.method != 1) throw halp::Error(LP_ERR_INVALID, "method must be 0 or 1");
+  if (o.method < 0 || o.method > 2) throw halp::Error(LP_ERR_INVALID, "method must be 0, 1 or 2");
   if (o.precision != 0 && o.precision != 1) throw halp::Error(LP_ERR_INVALID, "precision must be 0 or 1");
   if (o.check_every < 1 || o.chunk < 1 || o.chunk > 4096)
     throw halp::Error(LP_ERR_INVALID, "check_every >= 1 and 1 <= chunk <= 4096 required");
@@ -625,7 +625,7 @@ halp::Problem request_problem(const Request& r) {
 // spaces for a reference mix of n = 4 m and nnz = 36 m (the batched sizes)
 bool server_caps(int64_t budget, int precision, int64_t* cap_m, int64_t* cap_n, int64_t* cap_nz) {
   const int64_t sz = precision == 1 ? 4 : 8;
-  const int64_t per_row = 4 + 24 + 9 * sz, per_col = 4 + 40 + 10 * sz;
+  const int64_t per_row = 4 + 24 + 10 * sz, per_col = 4 + 40 + 11 * sz;
   const int64_t per_nz = 24 + (precision == 1 ? 8 : 0);
   const int64_t unit = per_row + 4 * per_col + 36 * per_nz;
   const int64_t u = budget / unit;

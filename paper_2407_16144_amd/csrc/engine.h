@@ -27,7 +27,9 @@ struct Problem {  // one input LP; pointers are host or device memory
 };
 
 struct Options {
-  int method = 1;  // 0 rHPDHG, 1 r2HPDHG
+  int method = 1;  // 0 rHPDHG, 1 r2HPDHG, 2 restarted average PDHG (the comparison method)
+  double avg_beta_sufficient = 0.2;  // average PDHG: KKT decay that restarts by itself
+  double avg_beta_necessary = 0.8;   // ... that restarts when the last check made no progress
   int precision = 0;  // 0 fp64, 1 fp32
   int ruiz_iters = 10;
   double pc_alpha = 1.0;

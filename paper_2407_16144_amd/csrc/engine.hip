@@ -248,7 +248,7 @@ class Engine final : public EngineBase {
 
   int64_t footprint(int64_t n, int64_t m, int64_t nnz) const override {
     const int64_t s = sizeof(T);
-    const int64_t per_row = 4 + 3 * 8 + 9 * s, per_col = 4 + 5 * 8 + 10 * s;
+    const int64_t per_row = 4 + 3 * 8 + 10 * s, per_col = 4 + 5 * 8 + 11 * s;
     const int64_t per_nz = 8 + 16 + (sizeof(T) == 8 ? 0 : 2 * s);
     return per_row * (m + 1) + per_col * (n + 1) + per_nz * nnz;
   }
@@ -305,12 +305,12 @@ class Engine final : public EngineBase {
   int32_t* K_rp = nullptr;
   double *q_o = nullptr, *Dr = nullptr, *fm = nullptr;
   T *q = nullptr, *y = nullptr, *y0 = nullptr, *yT = nullptr, *dy = nullptr, *kxbar = nullptr,
-    *kxp = nullptr, *cy1 = nullptr, *cy2 = nullptr;
+    *kxp = nullptr, *cy1 = nullptr, *cy2 = nullptr, *ys = nullptr;
   // n-space
   int32_t* KT_rp = nullptr;
   double *c_o = nullptr, *l_o = nullptr, *u_o = nullptr, *Dc = nullptr, *fn = nullptr;
   T *c = nullptr, *l = nullptr, *u = nullptr, *x = nullptr, *x0 = nullptr, *xbar = nullptr,
-    *xT = nullptr, *ktyp = nullptr, *cx1 = nullptr, *cx2 = nullptr;
+    *xT = nullptr, *ktyp = nullptr, *cx1 = nullptr, *cx2 = nullptr, *xs = nullptr;
   // column-sliced layout
   int32_t *brpK = nullptr, *brpKT = nullptr;
   T *spartD = nullptr, *spartP = nullptr;
@@ -356,10 +356,10 @@ void Engine<T>::allocate() {
   dalloc(&q_o, MS_);
   dalloc(&Dr, MS_);
   dalloc(&fm, MS_);
-  for (T** p : {&q, &y, &y0, &yT, &dy, &kxbar, &kxp, &cy1, &cy2}) dalloc(p, MS_);
+  for (T** p : {&q, &y, &y0, &yT, &dy, &kxbar, &kxp, &cy1, &cy2, &ys}) dalloc(p, MS_);
   dalloc(&KT_rp, NS_);
   for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dalloc(p, NS_);
-  for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2}) dalloc(p, NS_);
+  for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2, &xs}) dalloc(p, NS_);
   dalloc(&brpK, 2 * kSlices * MS_);
   dalloc(&brpKT, 2 * kSlices * NS_);
   dalloc(&d_st, nslots_);
@@ -398,10 +398,10 @@ void Engine<T>::release_all() {
   dfree(q_o);
   dfree(Dr);
   dfree(fm);
-  for (T** p : {&q, &y, &y0, &yT, &dy, &kxbar, &kxp, &cy1, &cy2}) dfree(*p);
+  for (T** p : {&q, &y, &y0, &yT, &dy, &kxbar, &kxp, &cy1, &cy2, &ys}) dfree(*p);
   dfree(KT_rp);
   for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dfree(*p);
-  for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2}) dfree(*p);
+  for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2, &xs}) dfree(*p);
   dfree(brpK);
   dfree(brpKT);
   dfree(spartD);
@@ -450,6 +450,7 @@ IterArgs<T> Engine<T>::args() const {
   A.ktyp = ktyp;
   A.cx1 = cx1;
   A.cx2 = cx2;
+  A.xs = xs;
   A.q = q;
   A.Dr = Dr;
   A.y = y;
@@ -460,6 +461,7 @@ IterArgs<T> Engine<T>::args() const {
   A.kxp = kxp;
   A.cy1 = cy1;
   A.cy2 = cy2;
+  A.ys = ys;
   A.st = d_st;
   A.gbase = d_gbase;
   A.cnt = d_cnt;
@@ -928,6 +930,11 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
       s.tau = eta / omega;
       s.sigma = eta * omega;
       s.reflect = opt_.method == 1;
+      s.avg = opt_.method == 2;
+      s.avg_b1 = opt_.avg_beta_sufficient;
+      s.avg_b2 = opt_.avg_beta_necessary;
+      s.kkt_anchor = NAN;
+      s.kkt_prev = INFINITY;
       s.C = opt_.check_every;
       s.primal_weight = opt_.primal_weight;
       s.beta = opt_.restart_beta;

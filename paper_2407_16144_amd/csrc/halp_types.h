@@ -90,7 +90,10 @@ struct alignas(16) InstState {
   // restart rule: 0 adaptive (eq. (adaptive-restart) + artificial), 1 fixed
   // frequency (eq. (fixed-restart), k >= fixed_len), 2 none
   int64_t fixed_len;
-  int32_t restart_mode, pad1;
+  int32_t restart_mode, avg;         // avg = 1: restarted average PDHG (plain T steps, average candidate)
+  // average PDHG's KKT-based restart: error at the epoch's start and at its
+  // previous check, and the sufficient / necessary decay factors
+  double kkt_anchor, kkt_prev, avg_b1, avg_b2;
   // power iteration
   double pw_scale, pw_prev, sigma_hat;
   int32_t pw_iter, pw_done;

@@ -29,6 +29,7 @@ struct IterArgs {
   T* ktyp;   // K^T y+ at the last eval
   T* cx1;    // dual-infeasibility ray candidates (recession-projected)
   T* cx2;
+  T* xs;     // average PDHG: sum of the epoch's iterates x^{n,0..k}
   // m-space
   const T* q;
   const double* Dr;
@@ -40,6 +41,7 @@ struct IterArgs {
   T* kxp;    // K x+ at the last eval
   T* cy1;    // primal-infeasibility ray candidates (clamped)
   T* cy2;
+  T* ys;     // average PDHG: sum of the epoch's iterates y^{n,0..k}
   // slice partial row sums of sliced row groups: [3][kSlices][space]
   T* spartD;   // m-space (dual step)
   T* spartP;   // n-space (primal step)

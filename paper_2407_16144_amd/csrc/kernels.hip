@@ -380,9 +380,18 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
       const T xp = clampT<T>(xo - tau * (cj - kty), lj, uj);
       const T xb = (T)2 * xp - xo;
       const int64_t k = g - S.kbase;
-      const double w = (double)(k + 1) / (double)(k + 2);
-      const T xh = S.reflect ? xb : xp;
-      const T xn = (T)w * xh + (T)(1.0 - w) * x0j;
+      T xn, xc = xp;  // next iterate; check candidate (T(z), or the epoch average)
+      if (S.avg) {
+        // plain PDHG step; running sum of z^{n,0..k+1} (restarted at k = 0)
+        const T xsum = (k == 0 ? xo : A.xs[j]) + xp;
+        A.xs[j] = xsum;
+        xn = xp;
+        if (mode == M_CHECK) xc = xsum / (T)(k + 2);
+      } else {
+        const double w = (double)(k + 1) / (double)(k + 2);
+        const T xh = S.reflect ? xb : xp;
+        xn = (T)w * xh + (T)(1.0 - w) * x0j;
+      }
       A.xbar[j] = xb;
       A.x[j] = xn;
       if (resid) {
@@ -390,16 +399,16 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
         const double d = (double)xo - (double)xp;
         ps[0] = d * d;
       } else if (mode == M_CHECK) {
-        A.xT[j] = xp;
+        A.xT[j] = xc;
         const double d = (double)xo - (double)xp;
-        const double ad = (double)xp - (double)x0j;
+        const double ad = (double)xc - (double)x0j;
         const T d1 = rec_proj<T>(xp - xo, lf, uf);
         const T d2 = rec_proj<T>(xo - x0j, lf, uf);
         A.cx1[j] = d1;
         A.cx2[j] = d2;
         ps[0] = d * d;
         ps[1] = ad * ad;
-        ps[2] = (double)cj * (double)xp;
+        ps[2] = (double)cj * (double)xc;
         ps[3] = (double)cj * (double)d1;
         ps[4] = (double)cj * (double)d2;
       }
@@ -543,10 +552,19 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
     return;
   }
   bool restart = false;
-  if (S.restart_mode == 0)
-    restart = (S.nrest == 0) || (res <= S.beta * S.r0) || (S.artificial > 0.0 && (double)k >= S.artificial * (double)t);
+  const bool artificial = S.artificial > 0.0 && (double)k >= S.artificial * (double)t;
+  if (S.restart_mode == 0 && S.avg)
+    restart = (S.nrest == 0) || (kkt <= S.avg_b1 * S.kkt_anchor) ||
+              (kkt <= S.avg_b2 * S.kkt_anchor && kkt > S.kkt_prev) || artificial;
+  else if (S.restart_mode == 0)
+    restart = (S.nrest == 0) || (res <= S.beta * S.r0) || artificial;
   else if (S.restart_mode == 1)
     restart = k >= S.fixed_len;
+  S.kkt_prev = kkt;
+  if (restart) {
+    S.kkt_anchor = kkt;
+    S.kkt_prev = INFINITY;
+  }
   if (restart) {
     const double dX = sqrt(S.acc[A_AX2]), dY = sqrt(S.acc[A_AY2]);
     if (S.primal_weight && dX > 1e-10 && dY > 1e-10 && isfinite(dX) && isfinite(dY))
@@ -642,16 +660,24 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
       if (ineq) yp = fmax(yp, (T)0);
       const T yb = (T)2 * yp - yo;
       const int64_t k = g - S.kbase;
-      const double w = (double)(k + 1) / (double)(k + 2);
-      const T yh = S.reflect ? yb : yp;
-      A.y[i] = (T)w * yh + (T)(1.0 - w) * y0i;
+      T yc = yp;  // check candidate
+      if (S.avg) {
+        const T ysum = (k == 0 ? yo : A.ys[i]) + yp;
+        A.ys[i] = ysum;
+        A.y[i] = yp;
+        if (mode == M_CHECK) yc = ysum / (T)(k + 2);
+      } else {
+        const double w = (double)(k + 1) / (double)(k + 2);
+        const T yh = S.reflect ? yb : yp;
+        A.y[i] = (T)w * yh + (T)(1.0 - w) * y0i;
+      }
       if (resid) {
         A.y0[i] = yo;
         const double d = (double)yo - (double)yp;
         ps[0] = d * d;
         ps[1] = d * (0.5 * ((double)kxpi - (double)s0));
       } else if (mode == M_CHECK) {
-        A.yT[i] = yp;
+        A.yT[i] = yc;
         const T dyv = yo - yp;
         A.dy[i] = dyv;
         A.kxbar[i] = s0;
@@ -662,10 +688,10 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
         }
         A.cy1[i] = e1;
         A.cy2[i] = e2;
-        const double ad = (double)yp - (double)y0i;
+        const double ad = (double)yc - (double)y0i;
         ps[0] = (double)dyv * (double)dyv;
         ps[1] = ad * ad;
-        ps[2] = (double)qi * (double)yp;
+        ps[2] = (double)qi * (double)yc;
         ps[3] = (double)qi * (double)e1;
         ps[4] = (double)qi * (double)e2;
       }

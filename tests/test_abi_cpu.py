@@ -53,7 +53,8 @@ def test_struct_layouts_match_header():
 
 def test_enum_values_match_header():
     src = open(HEADER).read()
-    for name in ["LP_RESTART_ADAPTIVE", "LP_RESTART_FIXED", "LP_RESTART_NONE", "LP_OPTIMAL",
+    for name in ["LP_METHOD_RHPDHG", "LP_METHOD_R2HPDHG", "LP_METHOD_RAPDHG",
+                 "LP_RESTART_ADAPTIVE", "LP_RESTART_FIXED", "LP_RESTART_NONE", "LP_OPTIMAL",
                  "LP_PRIMAL_INFEASIBLE", "LP_DUAL_INFEASIBLE", "LP_ITER_LIMIT"]:
         m = re.search(name + r"\s*=\s*(\d+)", src)
         assert m, name

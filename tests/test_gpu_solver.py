@@ -21,7 +21,8 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-METHODS = [("rhpdhg", halp.LP_METHOD_RHPDHG), ("r2hpdhg", halp.LP_METHOD_R2HPDHG)]
+METHODS = [("rhpdhg", halp.LP_METHOD_RHPDHG), ("r2hpdhg", halp.LP_METHOD_R2HPDHG),
+           ("rapdhg", halp.LP_METHOD_RAPDHG)]
 
 
 def _rel(a, b):
