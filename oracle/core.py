@@ -385,8 +385,11 @@ def _solve_average(lp, opts, P, K0, eta, sigma_hat, piters, omega, x, y) -> Resu
         if k > 0 and k % C == 0:
             xa, ya = sx / cnt, sy / cnt
             kkt, parts = rel_kkt(lp, P.Dc * xa, P.Dr * ya, K0)
+            thr = [b * kkt_anchor for b in (opts.avg_beta_sufficient, opts.avg_beta_necessary)] + [kkt_prev]
+            thr = [v for v in thr if math.isfinite(v) and v > 0.0]
             entry = dict(t=t, n=nrest, k=k, kkt=kkt, kkt_anchor=kkt_anchor, kkt_prev=kkt_prev,
-                         restart=False)
+                         restart=False,
+                         margin=min((abs(kkt - v) / v for v in thr), default=float("inf")))
             log.append(entry)
             if not np.isfinite(kkt):
                 return finish(NUMERICAL, xa, ya)
