@@ -200,6 +200,7 @@ def run_batch(args):
                       "statuses": {"optimal": st.count(1), "primal_infeasible": st.count(2),
                                    "dual_infeasible": st.count(3), "limit": st.count(4) + st.count(5)},
                       "max_iters": max(r["iters"] for r in res),
+                      "iters_sgm10": round(math.exp(sum(math.log(r["iters"] + 10) for r in res) / len(res)) - 10, 1),
                       "p50_latency_s": round(_pct(lat, 0.5), 3), "p99_latency_s": round(_pct(lat, 0.99), 3)},
            "roofline": roofline}
     if args.serial_baseline:
