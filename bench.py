@@ -289,14 +289,15 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
     ap.add_argument("--time-limit", type=float, default=600.0)
-    ap.add_argument("--workload", default="large", choices=["large", "mixed", "tiny", "batch", "serve"])
+    ap.add_argument("--workload", default="large", choices=["large", "mixed", "tiny", "batch", "serve", "mps"])
+    ap.add_argument("--mps", default=None, help="workload mps: the LP to solve (.mps or .mps.gz)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--requests", type=int, default=1200)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--serial-baseline", type=int, default=0,
                     help="batch/serve: also solve the first N LPs one at a time (FP64 rHPDHG)")
-    ap.add_argument("--profile-every", type=int, default=8)
+    ap.add_argument("--profile-every", type=int, default=32)
     ap.add_argument("--verbose", type=int, default=20, help="library progress line every N seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=float, default=0.0,
@@ -330,7 +331,13 @@ def main():
         torch.cuda.synchronize()
         print(f"copy probe: neg kernel reads and writes {nel * 8} bytes per launch", file=sys.stderr,
               flush=True)
-    lp = {"large": lpgen.large_single, "mixed": lpgen.large_mixed, "tiny": lpgen.tiny}[args.workload]()
+    if args.workload == "mps":
+        from paper_2407_16144_amd import mps
+        if not args.mps:
+            ap.error("--workload mps needs --mps FILE")
+        lp = mps.read(args.mps)
+    else:
+        lp = {"large": lpgen.large_single, "mixed": lpgen.large_mixed, "tiny": lpgen.tiny}[args.workload]()
     dev = torch.device("cuda", 0)
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
     tens = (T(lp.rowptr, torch.int32), T(lp.col, torch.int32), T(lp.val, torch.float64),
@@ -394,8 +401,8 @@ def main():
     dom = max(avg, key=lambda k: avg[k])
     achieved = byname[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     tstep = sum(avg.values())
-    wl_key = f"{args.workload}-{args.precision}"
-    tr = measured_traffic(wl_key, names[dom] + ("<double>" if s == 8 else "<float>"))
+    wl_key = f"{args.workload}-{args.precision}" if args.workload != "mps" else None
+    tr = measured_traffic(wl_key, names[dom] + ("<double>" if s == 8 else "<float>")) if wl_key else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
                 "kernel": names[dom], "bytes_per_launch": int(byname[dom]),
@@ -411,9 +418,11 @@ def main():
         "value": round(value, 5), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "mps file" if args.workload == "mps" else "synthetic",
         "config": {"workload": f"single LP {lp.m_eq}+{lp.m_ineq} rows x {lp.n} vars, "
-                               f"{lp.nnz} nnz, power-law rows, tol {args.tol:g}",
+                               f"{lp.nnz} nnz, " + (f"from {args.mps}" if args.workload == "mps"
+                                                   else "power-law rows") + f", tol {args.tol:g}",
                    "method": args.method, "precision": args.precision,
                    "iterations": iters, "iterations_per_s": round(iters / (wall / args.steps), 1),
                    "p50_latency_s": round(p50, 3), "p99_latency_s": round(p99, 3),

@@ -486,3 +486,21 @@ def test_server_results_equal_single_results(prec):
             assert rb["polish_iters"] > 0
             kkt, parts = oracle.rel_kkt(lp, xb, yb)
             assert kkt <= 1e-6 * (1 + 1e-6), parts
+
+
+def test_mps_model_solves():
+    """An LP read from MPS (maximisation, ranged row, objective constant) is
+    solved to the optimum HiGHS finds for the same model typed in directly."""
+    from scipy.optimize import linprog
+    from paper_2407_16144_amd import mps
+    import os
+    m = mps.read(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "small_model.mps"))
+    print("case mps", flush=True)
+    res = linprog(c=[-3, -2, 1, -4],
+                  A_ub=[[1, 2, 0, 1], [0, -1, -1, 0], [0, 1, 0, 3], [0, -1, 0, -3]],
+                  b_ub=[10, -2, 8, -3], A_eq=[[1, 0, -1, 0]], b_eq=[1],
+                  bounds=[(0, 4), (None, 6), (-2, 3), (0, 2.5)], method="highs")
+    for code in (halp.LP_METHOD_R2HPDHG, halp.LP_METHOD_RAPDHG):
+        r, x, y, _ = _gpu(m, 1e-9, 200_000, method=code)
+        assert r["status"] == halp.LP_OPTIMAL
+        assert m.objective(x) == pytest.approx(-res.fun + 1.5, rel=1e-7, abs=1e-7)
