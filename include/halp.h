@@ -140,6 +140,12 @@ typedef struct {
   int power_iters;
   int64_t polish_iters;     /* FP64 iterations after an FP32 phase (0 if none) */
   double seconds;           /* wall time of the last lp_solve / batch solve */
+  int64_t active_changes;   /* two-stage diagnostics (Section 4): variables whose T(z) sits
+                               at a different bound (or leaves / reaches one) and
+                               inequality rows whose dual leaves / reaches zero, between
+                               the last two checks of the final phase */
+  int64_t ident_iters;      /* iterations at the last check where any activity changed:
+                               the observed end of the identification stage */
 } lp_result;
 
 /* Fills *opt with the defaults listed above. */

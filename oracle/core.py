@@ -156,6 +156,30 @@ def m_norm(P: ScaledLP, dx, dy, tau, sigma):
     return math.sqrt(max(v, 0.0))
 
 
+class _Activity:
+    """Two-stage diagnostics (Section 4: identification, then local
+    convergence): at each check, the activity of T(z) = (x+, y+) -- each x+_j
+    at its lower bound (1), at its upper bound (2) or inside (0), each
+    inequality row's y+_i at zero (1) or not (0) -- compared with the
+    previous check's.  The first check only records."""
+
+    def __init__(self):
+        self.prev = None
+        self.changes = 0
+        self.ident = 0
+
+    def update(self, P, m_eq, xp, yp, t):
+        ax = np.where(np.isfinite(P.l) & (xp == P.l), 1, np.where(np.isfinite(P.u) & (xp == P.u), 2, 0))
+        ay = np.zeros(yp.shape[0], dtype=np.int64)
+        ay[m_eq:] = (yp[m_eq:] == 0.0)
+        if self.prev is not None:
+            self.changes = int(np.count_nonzero(ax != self.prev[0]) + np.count_nonzero(ay != self.prev[1]))
+            if self.changes > 0:
+                self.ident = t
+        self.prev = (ax, ay)
+        return self.changes
+
+
 def halpern_point(xp, yp, x, y, x0, y0, k, reflect):
     """Halpern step (eq. (hpdhg)) or reflected Halpern step (eq. (hrpdhg)):
     z^{k+1} = (k+1)/(k+2) * That + 1/(k+2) * z^0, with That = T(z^k) or
@@ -216,6 +240,8 @@ class Result:
     ray: np.ndarray | None = None
     log: list = field(default_factory=list)
     scaled: ScaledLP | None = None
+    active_changes: int = 0   # activity changes between the last two checks
+    ident_iters: int = 0      # iterations at the last check with an activity change
 
 
 def solve(lp, opts: Options | None = None) -> Result:
@@ -274,11 +300,13 @@ def solve(lp, opts: Options | None = None) -> Result:
     C = opts.check_every
     log = []
 
+    act = _Activity()
+
     def finish(status, xp, yp, ray=None):
         xu, yu = P.Dc * xp, P.Dr * yp
         kkt, parts = rel_kkt(lp, xu, yu, K0)
         return Result(status, xu, yu, t, nrest, kkt, parts["pobj"], parts["dobj"], parts,
-                      omega, eta, sigma_hat, piters, ray, log, P)
+                      omega, eta, sigma_hat, piters, ray, log, P, act.changes, act.ident)
 
     if opts.method == "rapdhg":
         return _solve_average(lp, opts, P, K0, eta, sigma_hat, piters, omega, x, y)
@@ -296,7 +324,8 @@ def solve(lp, opts: Options | None = None) -> Result:
             xu, yu = P.Dc * xp, P.Dr * yp
             kkt, parts = rel_kkt(lp, xu, yu, K0)
             entry = dict(t=t, n=nrest, k=k, kkt=kkt, resid=res, r0=r0, restart=False,
-                         margin=abs(res - opts.restart_beta * r0) / r0 if r0 > 0 else float("inf"))
+                         margin=abs(res - opts.restart_beta * r0) / r0 if r0 > 0 else float("inf"),
+                         active_changes=act.update(P, lp.m_eq, xp, yp, t))
             log.append(entry)
             if not np.isfinite(kkt) or not np.isfinite(res):
                 return finish(NUMERICAL, xp, yp)
@@ -367,11 +396,13 @@ def _solve_average(lp, opts, P, K0, eta, sigma_hat, piters, omega, x, y) -> Resu
     C = opts.check_every
     log = []
 
+    act = _Activity()
+
     def finish(status, xc, yc, ray=None):
         xu, yu = P.Dc * xc, P.Dr * yc
         kkt, parts = rel_kkt(lp, xu, yu, K0)
         return Result(status, xu, yu, t, nrest, kkt, parts["pobj"], parts["dobj"], parts,
-                      omega, eta, sigma_hat, piters, ray, log, P)
+                      omega, eta, sigma_hat, piters, ray, log, P, act.changes, act.ident)
 
     while True:
         xp, yp = pdhg_T(P, x, y, tau, sigma)
@@ -389,7 +420,8 @@ def _solve_average(lp, opts, P, K0, eta, sigma_hat, piters, omega, x, y) -> Resu
             thr = [v for v in thr if math.isfinite(v) and v > 0.0]
             entry = dict(t=t, n=nrest, k=k, kkt=kkt, kkt_anchor=kkt_anchor, kkt_prev=kkt_prev,
                          restart=False,
-                         margin=min((abs(kkt - v) / v for v in thr), default=float("inf")))
+                         margin=min((abs(kkt - v) / v for v in thr), default=float("inf")),
+                         active_changes=act.update(P, lp.m_eq, xp, yp, t))
             log.append(entry)
             if not np.isfinite(kkt):
                 return finish(NUMERICAL, xa, ya)

@@ -54,7 +54,8 @@ class lp_result(C.Structure):
                 ("dobj", C.c_double), ("rel_kkt", C.c_double), ("rel_primal", C.c_double),
                 ("rel_dual", C.c_double), ("rel_gap", C.c_double), ("omega", C.c_double),
                 ("eta", C.c_double), ("sigma_hat", C.c_double), ("power_iters", C.c_int),
-                ("polish_iters", C.c_int64), ("seconds", C.c_double)]
+                ("polish_iters", C.c_int64), ("seconds", C.c_double), ("active_changes", C.c_int64),
+                ("ident_iters", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

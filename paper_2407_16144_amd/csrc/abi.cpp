@@ -102,6 +102,8 @@ lp_result to_result(const halp::Result& r, double seconds) {
   o.sigma_hat = r.sigma_hat;
   o.power_iters = r.power_iters;
   o.seconds = seconds;
+  o.active_changes = r.active_changes;
+  o.ident_iters = r.ident_iters;
   return o;
 }
 
@@ -309,6 +311,7 @@ lp_result polish_result(const Polish& P, int i, halp::EngineBase& src, int src_i
   if (P.eng && i < (int)P.id.size() && P.id[i] >= 0) {
     lp_result o = to_result(P.eng->result(P.id[i]), seconds);
     o.polish_iters = o.iters;
+    o.ident_iters = o.ident_iters > 0 ? o.ident_iters + P.first[i].iters : P.first[i].ident_iters;
     o.iters += P.first[i].iters;
     o.restarts += P.first[i].restarts;
     o.checks += P.first[i].checks;
@@ -847,6 +850,7 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
         s->slot_ticket64.erase(slot);
         lp_result o = to_result(s->eng64->result(slot), 0.0);
         o.polish_iters = o.iters;
+        o.ident_iters = o.ident_iters > 0 ? o.ident_iters + r.first.iters : r.first.ident_iters;
         o.iters += r.first.iters;
         o.restarts += r.first.restarts;
         o.checks += r.first.checks;

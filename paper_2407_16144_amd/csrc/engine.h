@@ -77,6 +77,7 @@ struct Result {
   double omega = 0, eta = 0, sigma_hat = 0;
   int power_iters = 0, ray = 0;
   double seconds = 0;
+  int64_t active_changes = 0, ident_iters = 0;
 };
 
 class Error : public std::runtime_error {

@@ -314,6 +314,7 @@ class Engine final : public EngineBase {
   // column-sliced layout
   int32_t *brpK = nullptr, *brpKT = nullptr;
   T *spartD = nullptr, *spartP = nullptr;
+  uint8_t *actx = nullptr, *acty = nullptr;  // activity at the last check (two-stage diagnostics)
   Blk *d_schedPS = nullptr, *d_schedDS = nullptr;
   int64_t capPS_ = 0, capDS_ = 0, nPS_ = 0, nDS_ = 0;
   // control
@@ -360,6 +361,8 @@ void Engine<T>::allocate() {
   dalloc(&KT_rp, NS_);
   for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dalloc(p, NS_);
   for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2, &xs}) dalloc(p, NS_);
+  dalloc(&actx, NS_);
+  dalloc(&acty, MS_);
   dalloc(&brpK, 2 * kSlices * MS_);
   dalloc(&brpKT, 2 * kSlices * NS_);
   dalloc(&d_st, nslots_);
@@ -402,6 +405,8 @@ void Engine<T>::release_all() {
   dfree(KT_rp);
   for (double** p : {&c_o, &l_o, &u_o, &Dc, &fn}) dfree(*p);
   for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2, &xs}) dfree(*p);
+  dfree(actx);
+  dfree(acty);
   dfree(brpK);
   dfree(brpKT);
   dfree(spartD);
@@ -451,6 +456,7 @@ IterArgs<T> Engine<T>::args() const {
   A.cx1 = cx1;
   A.cx2 = cx2;
   A.xs = xs;
+  A.actx = actx;
   A.q = q;
   A.Dr = Dr;
   A.y = y;
@@ -462,6 +468,7 @@ IterArgs<T> Engine<T>::args() const {
   A.cy1 = cy1;
   A.cy2 = cy2;
   A.ys = ys;
+  A.acty = acty;
   A.st = d_st;
   A.gbase = d_gbase;
   A.cnt = d_cnt;
@@ -900,8 +907,8 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
         }
       }
     }
-    init_primal_kernel<T><<<gP, kThreads, 0, stream_>>>(d_nP, l, u, x, x0);
-    init_dual_kernel<T><<<gD, kThreads, 0, stream_>>>(d_nD, y, y0);
+    init_primal_kernel<T><<<gP, kThreads, 0, stream_>>>(d_nP, l, u, x, x0, actx);
+    init_dual_kernel<T><<<gD, kThreads, 0, stream_>>>(d_nD, y, y0, acty);
     HIPCHECK(hipGetLastError());
 
     // step size and primal weight, then park the LPs until set_params
@@ -935,6 +942,8 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
       s.avg_b2 = opt_.avg_beta_necessary;
       s.kkt_anchor = NAN;
       s.kkt_prev = INFINITY;
+      s.act_changes = 0;
+      s.ident_iters = 0;
       s.C = opt_.check_every;
       s.primal_weight = opt_.primal_weight;
       s.beta = opt_.restart_beta;
@@ -1407,6 +1416,8 @@ Result Engine<T>::result(int id) {
   r.sigma_hat = s.sigma_hat;
   r.power_iters = s.pw_iter;
   r.ray = s.ray;
+  r.active_changes = s.act_changes;
+  r.ident_iters = s.ident_iters;
   return r;
 }
 

@@ -62,6 +62,7 @@ __host__ __device__ inline int32_t blk_meta(int kind, int nsl, int slice) {
 enum AccSlot : int {
   A_DX2 = 0, A_AX2, A_POBJ, A_CD1, A_CD2,       // from the primal kernel
   A_DY2, A_AY2, A_DOBJQ, A_QY1, A_QY2,          // from the dual kernel
+  A_ACTX, A_ACTY,                               // activity changes (primal, dual)
 };
 
 struct alignas(16) InstState {
@@ -94,6 +95,10 @@ struct alignas(16) InstState {
   // average PDHG's KKT-based restart: error at the epoch's start and at its
   // previous check, and the sufficient / necessary decay factors
   double kkt_anchor, kkt_prev, avg_b1, avg_b2;
+  // two-stage diagnostics: variables / inequality rows whose activity (at a
+  // bound; dual at zero) changed between the last two checks, and the
+  // iteration count at the last check where any changed
+  int64_t act_changes, ident_iters;
   // power iteration
   double pw_scale, pw_prev, sigma_hat;
   int32_t pw_iter, pw_done;

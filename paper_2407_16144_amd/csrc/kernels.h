@@ -30,6 +30,7 @@ struct IterArgs {
   T* cx1;    // dual-infeasibility ray candidates (recession-projected)
   T* cx2;
   T* xs;     // average PDHG: sum of the epoch's iterates x^{n,0..k}
+  uint8_t* actx;  // activity of x+ at the last check: 1 at l, 2 at u, 0 inside, 255 none yet
   // m-space
   const T* q;
   const double* Dr;
@@ -42,6 +43,7 @@ struct IterArgs {
   T* cy1;    // primal-infeasibility ray candidates (clamped)
   T* cy2;
   T* ys;     // average PDHG: sum of the epoch's iterates y^{n,0..k}
+  uint8_t* acty;  // activity of y+ at the last check: 1 at zero (inequality rows), 0 else
   // slice partial row sums of sliced row groups: [3][kSlices][space]
   T* spartD;   // m-space (dual step)
   T* spartP;   // n-space (primal step)

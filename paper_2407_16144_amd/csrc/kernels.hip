@@ -411,6 +411,10 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
         ps[2] = (double)cj * (double)xc;
         ps[3] = (double)cj * (double)d1;
         ps[4] = (double)cj * (double)d2;
+        const uint8_t act = (lf && xp == lj) ? 1 : (uf && xp == uj) ? 2 : 0;
+        const uint8_t was = A.actx[j];
+        A.actx[j] = act;
+        ps[5] = (was != 255 && was != act) ? 1.0 : 0.0;
       }
     }
   }
@@ -485,6 +489,8 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
     S.acc[A_DOBJQ] = sd[2];
     S.acc[A_QY1] = sd[3];
     S.acc[A_QY2] = sd[4];
+    S.acc[A_ACTX] = sp[5];
+    S.acc[A_ACTY] = sd[5];
     S.phase = PH_EVAL;
     return;
   }
@@ -514,6 +520,8 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
   S.dobj = dobj;
   S.resid = res;
   S.iters = t;
+  S.act_changes = (int64_t)(S.acc[A_ACTX] + S.acc[A_ACTY]);
+  if (S.act_changes > 0) S.ident_iters = t;
   int st = ST_RUNNING;
   if (!isfinite(kkt) || !isfinite(res)) {
     st = ST_NUMERICAL;
@@ -694,6 +702,10 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
         ps[2] = (double)qi * (double)yc;
         ps[3] = (double)qi * (double)e1;
         ps[4] = (double)qi * (double)e2;
+        const uint8_t act = (ineq && yp == (T)0) ? 1 : 0;
+        const uint8_t was = A.acty[i];
+        A.acty[i] = act;
+        ps[5] = (was != 255 && was != act) ? 1.0 : 0.0;
       }
     }
   }
@@ -1112,7 +1124,7 @@ __global__ void transpose_rowptr_kernel(const int32_t* keys, int64_t nnz, int64_
 
 template <class T>
 __global__ __launch_bounds__(kThreads) void init_primal_kernel(const Blk* schedP, const T* l, const T* u,
-                                                               T* x, T* x0) {
+                                                               T* x, T* x0, uint8_t* actx) {
   const Blk b = schedP[blockIdx.x];
   const int nrows = b.r1 - b.r0;
   if ((int)threadIdx.x < nrows) {
@@ -1120,17 +1132,19 @@ __global__ __launch_bounds__(kThreads) void init_primal_kernel(const Blk* schedP
     const T v = clampT<T>((T)0, l[j], u[j]);
     x[j] = v;
     x0[j] = v;
+    actx[j] = 255;
   }
 }
 
 template <class T>
-__global__ __launch_bounds__(kThreads) void init_dual_kernel(const Blk* schedD, T* y, T* y0) {
+__global__ __launch_bounds__(kThreads) void init_dual_kernel(const Blk* schedD, T* y, T* y0, uint8_t* acty) {
   const Blk b = schedD[blockIdx.x];
   const int nrows = b.r1 - b.r0;
   if ((int)threadIdx.x < nrows) {
     const int64_t i = (int64_t)b.r0 + threadIdx.x;
     y[i] = (T)0;
     y0[i] = (T)0;
+    acty[i] = 255;
   }
 }
 
@@ -1224,10 +1238,11 @@ template __global__ void slice_scatter_kernel<float>(const int32_t*, const int32
 template __global__ void transpose_gather_kernel<double>(const int32_t*, const int32_t*, const double*,
                                                          int64_t, int64_t, int32_t*, double*);
 template __global__ void init_primal_kernel<double>(const Blk*, const double*, const double*, double*,
-                                                    double*);
-template __global__ void init_primal_kernel<float>(const Blk*, const float*, const float*, float*, float*);
-template __global__ void init_dual_kernel<double>(const Blk*, double*, double*);
-template __global__ void init_dual_kernel<float>(const Blk*, float*, float*);
+                                                    double*, uint8_t*);
+template __global__ void init_primal_kernel<float>(const Blk*, const float*, const float*, float*, float*,
+                                                   uint8_t*);
+template __global__ void init_dual_kernel<double>(const Blk*, double*, double*, uint8_t*);
+template __global__ void init_dual_kernel<float>(const Blk*, float*, float*, uint8_t*);
 template __global__ void unscale_kernel<double>(const double*, const double*, int64_t, int64_t, double*);
 template __global__ void unscale_kernel<float>(const float*, const double*, int64_t, int64_t, double*);
 template __global__ void load_point_kernel<double>(const double*, double*, double*, int64_t, int64_t);

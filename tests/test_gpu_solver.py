@@ -504,3 +504,17 @@ def test_mps_model_solves():
         r, x, y, _ = _gpu(m, 1e-9, 200_000, method=code)
         assert r["status"] == halp.LP_OPTIMAL
         assert m.objective(x) == pytest.approx(-res.fun + 1.5, rel=1e-7, abs=1e-7)
+
+
+
+@pytest.mark.parametrize("name,code", METHODS)
+@pytest.mark.parametrize("seed", [0, 3])
+def test_activity_diagnostics_match_oracle(name, code, seed):
+    """Two-stage diagnostics: the iteration of the last active-set change and
+    the last check's change count are the oracle's (integer parity)."""
+    lp = lpgen.tiny(seed)
+    print(f"case activity {name} seed={seed}", flush=True)
+    res, x, y, _ = _gpu(lp, 1e-10, 200_000, method=code)
+    ref = oracle.solve(lp, oracle.Options(method=name, tol=1e-10))
+    assert res["iters"] == ref.iters
+    assert res["ident_iters"] == ref.ident_iters and res["active_changes"] == ref.active_changes

@@ -378,6 +378,38 @@ def test_average_pdhg_restart_rule():
                 or e["k"] >= 0.36 * e["t"])
         assert e["restart"] == rule
 
+
+@pytest.mark.parametrize("method", ["rhpdhg", "r2hpdhg", "rapdhg"])
+def test_activity_settles_before_convergence(method):
+    """Section 4's two-stage picture: the active set of T(z) (x+ at a bound,
+    inequality duals at zero) stops changing in finite time, well before the
+    iterates converge (finite-time identification), and then stays fixed.
+    The count is checked against a direct recount from the logged states."""
+    lp = lpgen.tiny(0)
+    states = []
+
+    def cb(d):
+        states.append((d["t"], d["xp"].copy(), d["yp"].copy(), d["P"]))
+
+    r = oracle.solve(lp, oracle.Options(method=method, tol=1e-10, callback=cb))
+    assert r.status == core.OPTIMAL
+    assert 0 < r.ident_iters < 0.8 * r.iters
+    assert r.active_changes == 0
+    checks = [e for e in r.log]
+    assert all(e["active_changes"] == 0 for e in checks if e["t"] > r.ident_iters)
+    # recount from the T outputs at the check iterations
+    by_t = {t: (xp, yp, P) for t, xp, yp, P in states}
+    prev = None
+    for e in checks:
+        xp, yp, P = by_t[e["t"]]
+        ax = [(1 if np.isfinite(lo) and v == lo else 2 if np.isfinite(hi) and v == hi else 0)
+              for v, lo, hi in zip(xp, P.l, P.u)]
+        ay = [int(v == 0.0) for v in yp[lp.m_eq:]]
+        if prev is not None:
+            want = sum(a != b for a, b in zip(ax, prev[0])) + sum(a != b for a, b in zip(ay, prev[1]))
+            assert e["active_changes"] == want
+        prev = (ax, ay)
+
 # ---------------------------------------------------------------- whole solves
 
 def test_one_dimensional_example_limit():
