@@ -223,7 +223,7 @@ def run_serve(args):
     lps = [lpgen.request_instance(r) for r in trace]
     print(f"generated {len(lps)} requests in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
           flush=True)
-    opt = _opts(halp, args, use_graph=0)
+    opt = _opts(halp, args, use_graph=0 if args.no_graph else 1)
     h = halp.lp_server_create(int(args.budget_gb * 1e9), 512, opt=opt)
     try:
         t0 = halp.lp_server_clock(h)

@@ -438,8 +438,8 @@ def test_fp32_with_fp64_polish(on_device):
     assert abs(res["pobj"] - ref.pobj) <= 1e-8 * (1 + abs(ref.pobj))
 
 
-@pytest.mark.parametrize("prec", [halp.LP_PREC_FP64, halp.LP_PREC_FP32])
-def test_server_results_equal_single_results(prec):
+@pytest.mark.parametrize("prec,graph", [(halp.LP_PREC_FP64, 0), (halp.LP_PREC_FP32, 0), (halp.LP_PREC_FP64, 1)])
+def test_server_results_equal_single_results(prec, graph):
     """Continuous batching: LPs submitted at different times, admitted as
     memory frees up, give the same result as solving each alone.  FP32: each
     LP's FP32 phase and its FP64 polish phase run in the server's two
@@ -447,8 +447,8 @@ def test_server_results_equal_single_results(prec):
     lps = [lpgen.scaled_powerlaw(400 + i, m, 3 * m) for i, m in enumerate([50, 400, 120, 900, 30, 250])]
     lps.append(lpgen.add_contradictory_rows(lpgen.tiny(8), seed=3))
     lps.append(lpgen.add_unbounded_column(lpgen.scaled_powerlaw(6, 40, 120), seed=2))
-    print(f"case server precision={prec}", flush=True)
-    opt = halp.lp_default_options(use_graph=0, precision=prec)
+    print(f"case server precision={prec} graph={graph}", flush=True)
+    opt = halp.lp_default_options(use_graph=graph, precision=prec)
     phases = 2 if prec == halp.LP_PREC_FP32 else 1
     # a budget that holds only a few of these at once, and 3 slots
     h = halp.lp_server_create(40_000_000, 3, opt=opt)
