@@ -125,6 +125,9 @@ typedef struct {
                                LP_RESTART_FIXED (eq. (fixed-restart): at the first check
                                with k >= fixed_restart_len), LP_RESTART_NONE */
   int64_t fixed_restart_len; /* k* of LP_RESTART_FIXED (>= 1) */
+  int xcd_pin;              /* 1 (default): in schedules of 16 or more LPs, each LP's
+                               workgroups run on one XCD (its gathered vectors stay in
+                               that XCD's L2); 0: every LP spread over all XCDs */
 } lp_options;
 
 typedef struct {

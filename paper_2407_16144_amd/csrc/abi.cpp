@@ -66,6 +66,7 @@ halp::Options to_opts(const lp_options* o) {
   r.stall_checks = o->stall_checks;
   r.restart_mode = o->restart_mode;
   r.fixed_restart_len = o->fixed_restart_len;
+  r.xcd_pin = o->xcd_pin;
   return r;
 }
 
@@ -376,6 +377,7 @@ void lp_default_options(lp_options* o) {
   o->stall_checks = d.stall_checks;
   o->restart_mode = d.restart_mode;
   o->fixed_restart_len = d.fixed_restart_len;
+  o->xcd_pin = d.xcd_pin;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }

@@ -56,6 +56,7 @@ struct Options {
   // FP32 phase before an FP64 polish: an LP leaves it after this many checks
   // without a 10% drop of its best KKT error (its FP32 floor), 0: never
   int64_t stall_checks = 200;
+  int xcd_pin = 1;                 // with many LPs, run each LP's blocks on one XCD
   int restart_mode = 0;            // 0 adaptive, 1 fixed frequency, 2 none
   int64_t fixed_restart_len = 0;   // k* of the fixed-frequency rule
   int verbose = 0;

@@ -275,6 +275,7 @@ class Engine final : public EngineBase {
   void allocate();
   void release_all();
   void rebuild_schedules();
+  void pin_to_xcds(std::vector<Blk>& v, const std::vector<std::pair<int, int>>& ranges) const;
   void mark_streaming(const std::vector<int>& live, std::vector<Blk>& P, std::vector<Blk>& PS,
                       std::vector<Blk>& DS, std::vector<Blk>& D) const;
   int scheduled_ = 0;          // LPs in the current schedules
@@ -1094,6 +1095,37 @@ void Engine<T>::set_params(const std::vector<int>& ids, double tol, int64_t max_
   for (int k = 0; k < ni; ++k) h_status[0][ids[k]] = h_status[1][ids[k]] = cur[k].status;
 }
 
+// Many LPs in one schedule: each LP's blocks go to one XCD.  Workgroups are
+// dispatched round-robin over the 8 XCDs, so schedule position p runs on XCD
+// p % 8; LPs are assigned to 8 lanes (largest first, to the lane with the
+// fewest blocks) and lane q fills positions q, q + 8, ... (padded with no-op
+// blocks).  Each XCD's L2 then caches only the gathered vectors of its own
+// LPs instead of every running LP's.
+template <class T>
+void Engine<T>::pin_to_xcds(std::vector<Blk>& v, const std::vector<std::pair<int, int>>& ranges) const {
+  std::vector<int> order(ranges.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return ranges[a].second - ranges[a].first > ranges[b].second - ranges[b].first;
+  });
+  std::vector<std::vector<Blk>> lane(kSlices);
+  for (int i : order) {
+    int q = 0;
+    for (int k = 1; k < kSlices; ++k)
+      if (lane[k].size() < lane[q].size()) q = k;
+    for (int p = ranges[i].first; p < ranges[i].second; ++p) lane[q].push_back(v[p]);
+  }
+  size_t len = 0;
+  for (auto& l : lane) len = std::max(len, l.size());
+  Blk pad{};
+  pad.meta = blk_meta(BK_PAD, 1, 0);
+  std::vector<Blk> out;
+  out.reserve(len * kSlices);
+  for (size_t r = 0; r < len; ++r)
+    for (int q = 0; q < kSlices; ++q) out.push_back(r < lane[q].size() ? lane[q][r] : pad);
+  v.swap(out);
+}
+
 // The vectors of a step and the matrix tiles read before the cache budget is
 // used up are read normally and stay in the last-level cache from one step to
 // the next; the remaining tiles are streamed with non-temporal loads, so that
@@ -1158,6 +1190,15 @@ void Engine<T>::rebuild_schedules() {
     sched_size_[0] += (double)slots_[s].nnz;
     sched_size_[1] += (double)slots_[s].n;
     sched_size_[2] += (double)slots_[s].m;
+  }
+  if (opt_.xcd_pin && (int)live.size() >= kPinMinLPs) {
+    std::vector<std::pair<int, int>> rp, rd;
+    for (const int4& r : rg) {
+      rp.push_back({r.x, r.y});
+      rd.push_back({r.z, r.w});
+    }
+    pin_to_xcds(P, rp);
+    pin_to_xcds(D, rd);
   }
   mark_streaming(live, P, PS, DS, D);
   HIPCHECK(hipStreamSynchronize(stream_));

@@ -33,6 +33,7 @@ enum BlkKind : int { BK_STREAM = 0, BK_LONG = 1, BK_PAD = 2 };
 // workgroups (dispatched round-robin over the XCDs) gather from a slice of the
 // vector small enough to stay in that XCD's L2.
 constexpr int kSlices = 8;
+constexpr int kPinMinLPs = 16;   // schedules with at least this many LPs pin each LP to one XCD
 enum Status : int { ST_RUNNING = 0, ST_OPTIMAL = 1, ST_PRIMAL_INFEAS = 2, ST_DUAL_INFEAS = 3,
                     ST_ITER_LIMIT = 4, ST_TIME_LIMIT = 5, ST_NUMERICAL = 6 };
 

@@ -312,6 +312,7 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
   __shared__ double s_out[kNS];
 
   const Blk b = A.schedP[blockIdx.x];
+  if (blk_kind(b) == BK_PAD) return;
   const int nrows = b.r1 - b.r0;
   const int t = threadIdx.x;
   const bool own = t < nrows;
@@ -605,6 +606,7 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
   __shared__ int s_last;
 
   const Blk b = A.schedD[blockIdx.x];
+  if (blk_kind(b) == BK_PAD) return;
   const int nrows = b.r1 - b.r0;
   const int t = threadIdx.x;
   const bool own = t < nrows;

@@ -223,6 +223,30 @@ def test_batch_results_equal_single_results():
         halp.lp_batch_destroy(h)
 
 
+def test_xcd_pinned_batch_equals_spread_batch():
+    """A batch large enough to be pinned (each LP's workgroups on one XCD)
+    gives the same bits as the same batch spread over all XCDs and as the
+    single solves."""
+    lps = [lpgen.scaled_powerlaw(600 + i, m, 3 * m) for i, m in enumerate([40, 300, 75, 900, 10, 120] * 4)]
+    lps.append(lpgen.add_contradictory_rows(lpgen.tiny(8), seed=2))
+    print("case pinned batch", flush=True)
+    out = []
+    for pin in (1, 0):
+        h = halp.lp_batch_create(lps, opt=halp.lp_default_options(xcd_pin=pin))
+        try:
+            halp.lp_batch_solve(h, 1e-6, 100_000)
+            out.append([(halp.lp_batch_status(h, i).as_dict(), halp.lp_batch_get_solution(h, i, lp.n, lp.m))
+                        for i, lp in enumerate(lps)])
+        finally:
+            halp.lp_batch_destroy(h)
+    for i, lp in enumerate(lps):
+        (ra, (xa, ya)), (rb, (xb, yb)) = out[0][i], out[1][i]
+        assert ra["status"] == rb["status"] and ra["iters"] == rb["iters"], i
+        assert np.array_equal(xa, xb) and np.array_equal(ya, yb), i
+    for i in (0, 3, len(lps) - 1):
+        rs, xs, ys, _ = _gpu(lps[i], 1e-6, 100_000)
+        assert rs["iters"] == out[0][i][0]["iters"] and np.array_equal(xs, out[0][i][1][0])
+
 @pytest.mark.parametrize("graph", [0, 1])
 def test_graph_and_stream_launch_agree(graph):
     lp = lpgen.tiny(9)
