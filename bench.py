@@ -9,7 +9,7 @@ are resident in HBM (torch tensors) when the timed region starts; each step
 runs lp_create (validation, transpose, scaling, power iteration) and lp_solve
 to a relative KKT error of 1e-4, FP64, r2HPDHG, through the C ABI.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the solver runs on one GPU.
 """
 import argparse
 import json
@@ -304,11 +304,14 @@ def main():
                     help="first run a plain streaming kernel (y = -x, FP64) over this many MB "
                          "(calibration of the HBM byte counters)")
     ap.add_argument("--no-graph", action="store_true", help="launch steps without hipGraphs")
+    ap.add_argument("--autotune", action="store_true",
+                    help="single-LP workloads: pick the SpMV tile shapes by timing them first "
+                         "(outside the timed region; reported in config)")
     ap.add_argument("--cache-budget-mb", type=float, default=None,
                     help="bytes (MiB) of vectors and tiles kept in the last-level cache (< 0: all)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus})",
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
 
@@ -344,11 +347,21 @@ def main():
             T(lp.c, torch.float64), T(lp.rhs, torch.float64), T(lp.lb, torch.float64),
             T(lp.ub, torch.float64))
     stream = torch.cuda.current_stream()
+    tuned, tune_info = {}, None
+    if args.autotune:
+        from paper_2407_16144_amd import autotune
+        tuned, table, secs = autotune.autotune(lp, method=METHODS[args.method],
+                                               precision=1 if args.precision == "fp32" else 0,
+                                               **({} if args.cache_budget_mb is None else
+                                                  {"cache_budget_bytes": int(args.cache_budget_mb * 2**20)}))
+        tune_info = {"best": tuned, "seconds": round(secs, 2), "table": table}
+        print(f"autotune: {tuned} in {secs:.1f}s", file=sys.stderr, flush=True)
     opt = halp.lp_default_options(
         method=METHODS[args.method],
         precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64,
         profile=args.profile_every, verbose=args.verbose, use_graph=0 if args.no_graph else 1,
-        **({} if args.cache_budget_mb is None else {"cache_budget_bytes": int(args.cache_budget_mb * 2**20)}))
+        **({} if args.cache_budget_mb is None else {"cache_budget_bytes": int(args.cache_budget_mb * 2**20)}),
+        **tuned)
 
     def step():
         h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,
@@ -427,7 +440,8 @@ def main():
                    "iterations": iters, "iterations_per_s": round(iters / (wall / args.steps), 1),
                    "p50_latency_s": round(p50, 3), "p99_latency_s": round(p99, 3),
                    "rel_kkt": results[-1]["rel_kkt"], "status": halp.STATUS_NAMES[results[-1]["status"]],
-                   "power_iters": results[-1]["power_iters"]},
+                   "power_iters": results[-1]["power_iters"],
+                   **({"autotune": tune_info} if tune_info else {})},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -128,6 +128,12 @@ typedef struct {
   int xcd_pin;              /* 1 (default): in schedules of 16 or more LPs, each LP's
                                workgroups run on one XCD (its gathered vectors stay in
                                that XCD's L2); 0: every LP spread over all XCDs */
+  int tile_rows;            /* SpMV tile shapes (chosen by paper_2407_16144_amd.autotune):
+                               rows per plain workgroup tile, 1..256 (default 256; a
+                               tile holds at most 1024 entries, longer rows are split
+                               off into their own strided tiles) */
+  int slice_entries;        /* entries per column-slice tile: 256, 512 (default) or 1024 */
+  int slice_rows;           /* rows per sliced row group, 1..256 (default 128) */
 } lp_options;
 
 typedef struct {

@@ -67,11 +67,18 @@ halp::Options to_opts(const lp_options* o) {
   r.restart_mode = o->restart_mode;
   r.fixed_restart_len = o->fixed_restart_len;
   r.xcd_pin = o->xcd_pin;
+  r.tile_rows = o->tile_rows;
+  r.slice_entries = o->slice_entries;
+  r.slice_rows = o->slice_rows;
   return r;
 }
 
 void check_opts(const halp::Options& o) {
   if (o.restart_mode < 0 || o.restart_mode > 2) throw halp::Error(LP_ERR_INVALID, "restart_mode must be 0, 1 or 2");
+  if (o.tile_rows < 1 || o.tile_rows > halp::kMaxRows || o.slice_rows < 1 || o.slice_rows > halp::kMaxRows)
+    throw halp::Error(LP_ERR_INVALID, "tile_rows and slice_rows must be in 1..256");
+  if (o.slice_entries != 256 && o.slice_entries != 512 && o.slice_entries != 1024)
+    throw halp::Error(LP_ERR_INVALID, "slice_entries must be 256, 512 or 1024");
   if (o.restart_mode == 1 && o.fixed_restart_len < 1)
     throw halp::Error(LP_ERR_INVALID, "fixed restarts need fixed_restart_len >= 1");
   if (o.method < 0 || o.method > 2) throw halp::Error(LP_ERR_INVALID, "method must be 0, 1 or 2");
@@ -378,6 +385,9 @@ void lp_default_options(lp_options* o) {
   o->restart_mode = d.restart_mode;
   o->fixed_restart_len = d.fixed_restart_len;
   o->xcd_pin = d.xcd_pin;
+  o->tile_rows = d.tile_rows;
+  o->slice_entries = d.slice_entries;
+  o->slice_rows = d.slice_rows;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }

@@ -57,6 +57,9 @@ struct Options {
   // without a 10% drop of its best KKT error (its FP32 floor), 0: never
   int64_t stall_checks = 200;
   int xcd_pin = 1;                 // with many LPs, run each LP's blocks on one XCD
+  int tile_rows = kMaxRows;        // rows per plain workgroup tile (<= 256)
+  int slice_entries = kSliceNB;    // entries per slice tile: 256, 512 or 1024
+  int slice_rows = kSliceRows;     // rows per sliced row group (<= 256)
   int restart_mode = 0;            // 0 adaptive, 1 fixed frequency, 2 none
   int64_t fixed_restart_len = 0;   // k* of the fixed-frequency rule
   int verbose = 0;

@@ -91,7 +91,7 @@ static void dfree(P*& p) {
 // than NB entries gets a "long" block.  Every LP gets at least one block so
 // that its controller always runs.  gid counts blocks from 0 (offset when the
 // schedules of all LPs are concatenated).
-static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int inst, int NB,
+static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int inst, int NB, int max_rows,
                          std::vector<Blk>& out) {
   const size_t first = out.size();
   int64_t start = 0, acc = 0;
@@ -116,7 +116,7 @@ static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int ins
       acc = 0;
       continue;
     }
-    if (acc + len > NB || (r - start) >= kMaxRows) {
+    if (acc + len > NB || (r - start) >= max_rows) {
       if (r > start) emit(start, r, BK_STREAM);
       start = r;
       acc = 0;
@@ -128,7 +128,7 @@ static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int ins
 }
 
 // Column-sliced schedule of one LP's rows.  cnt[r * kSlices + s] counts row
-// r's entries in column slice s.  Rows are grouped (at most kSliceRows rows)
+// r's entries in column slice s.  Rows are grouped (at most max_rows rows)
 // so that every slice of a group holds at most NB entries (a row with more
 // gets a group of its own and "long" slice blocks).  Each group has kSlices
 // slice blocks in `sl` whose entries are stored group-major, then
@@ -136,7 +136,8 @@ static void build_blocks(const int32_t* rp, int64_t nrows, int64_t base, int ins
 // epilogue blocks (nsl = kSlices, kMaxRows rows each) that add up the
 // slice partial sums.  Row pointers of slice blocks go to brp (positions from brp_base);
 // dst[r * kSlices + s] receives the first position of row r's slice s.
-static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int inst, int NB, int64_t nz0,
+static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int inst, int NB, int max_rows,
+                         int64_t nz0,
                          int64_t brp_base, std::vector<Blk>& grp, std::vector<Blk>& sl,
                          std::vector<int32_t>& brp, std::vector<int32_t>& dst) {
   std::vector<std::pair<int64_t, int64_t>> groups;
@@ -149,7 +150,7 @@ static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int in
   };
   for (int64_t r = 0; r < nrows; ++r) {
     const int32_t* c = cnt + r * kSlices;
-    bool big = false, over = (r - start) >= kSliceRows;
+    bool big = false, over = (r - start) >= max_rows;
     for (int q = 0; q < kSlices; ++q) {
       big |= c[q] > NB;
       over |= acc[q] + c[q] > NB;
@@ -276,6 +277,7 @@ class Engine final : public EngineBase {
   void release_all();
   void rebuild_schedules();
   void pin_to_xcds(std::vector<Blk>& v, const std::vector<std::pair<int, int>>& ranges) const;
+  void launch_slices(bool dual, const IterArgs<T>& A, int step);
   void mark_streaming(const std::vector<int>& live, std::vector<Blk>& P, std::vector<Blk>& PS,
                       std::vector<Blk>& DS, std::vector<Blk>& D) const;
   int scheduled_ = 0;          // LPs in the current schedules
@@ -751,7 +753,7 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
   // 3. dual schedules, transpose, primal schedules
   for (size_t k = 0; k < probs.size(); ++k) {
     Slot& S = slots_[ids[k]];
-    build_blocks(host_rp[k].data(), S.m, S.row0, ids[k], NB, S.bD);
+    build_blocks(host_rp[k].data(), S.m, S.row0, ids[k], NB, opt_.tile_rows, S.bD);
     // host_rp holds space positions; build_blocks only uses differences
   }
   // contiguous groups transpose together
@@ -775,7 +777,7 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
     Slot& S = slots_[ids[t]];
     std::vector<int32_t> krp(S.n + 1);
     HIPCHECK(hipMemcpy(krp.data(), KT_rp + S.col0, sizeof(int32_t) * (S.n + 1), hipMemcpyDeviceToHost));
-    build_blocks(krp.data(), S.n, S.col0, ids[t], NB, S.bP);
+    build_blocks(krp.data(), S.n, S.col0, ids[t], NB, opt_.tile_rows, S.bP);
   }
 
   // 4. temporary schedules of the new LPs, preprocessing, power iteration
@@ -980,7 +982,7 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
 // (slices over its constraints) into the column-sliced layout.
 template <class T>
 void Engine<T>::slice_matrix(int id, bool dual) {
-  constexpr int NB = kSliceNB;
+  const int NB = opt_.slice_entries;
   Slot& S = slots_[id];
   const int64_t nrows = dual ? S.m : S.n;
   const int64_t r0 = dual ? S.row0 : S.col0;
@@ -1007,7 +1009,7 @@ void Engine<T>::slice_matrix(int id, bool dual) {
     dfree(d_cnt);
     throw Error(-2, "no room for sliced row pointers");
   }
-  build_sliced(cnt.data(), nrows, r0, id, NB, S.nz0, at, grp, sl, brp, dst);
+  build_sliced(cnt.data(), nrows, r0, id, NB, opt_.slice_rows, S.nz0, at, grp, sl, brp, dst);
   if ((int64_t)brp.size() > cap) throw Error(-3, "sliced row pointer overflow");
   ab.release(at + (int64_t)brp.size(), cap - (int64_t)brp.size());
   int32_t* brp_d = dual ? brpK : brpKT;
@@ -1243,6 +1245,25 @@ void Engine<T>::rebuild_schedules() {
 }
 
 template <class T>
+void Engine<T>::launch_slices(bool dual, const IterArgs<T>& A, int step) {
+  const unsigned g = (unsigned)(dual ? nDS_ : nPS_);
+  switch (opt_.slice_entries) {
+    case 256:
+      if (dual) dual_slice_step<T, 256><<<g, kThreads, 0, stream_>>>(A, step);
+      else primal_slice_step<T, 256><<<g, kThreads, 0, stream_>>>(A, step);
+      break;
+    case 1024:
+      if (dual) dual_slice_step<T, 1024><<<g, kThreads, 0, stream_>>>(A, step);
+      else primal_slice_step<T, 1024><<<g, kThreads, 0, stream_>>>(A, step);
+      break;
+    default:
+      if (dual) dual_slice_step<T, 512><<<g, kThreads, 0, stream_>>>(A, step);
+      else primal_slice_step<T, 512><<<g, kThreads, 0, stream_>>>(A, step);
+      break;
+  }
+}
+
+template <class T>
 void Engine<T>::launch_chunk() {
   if (sched_dirty_ && !compacted_) rebuild_schedules();
   if (nP_ == 0 || nD_ == 0) return;
@@ -1263,11 +1284,11 @@ void Engine<T>::launch_chunk() {
     for (int i = 0; i < CH; ++i) {
       hipEvent_t* e = timed ? &pev_[6 * i] : nullptr;
       if (timed) HIPCHECK(hipEventRecord(e[0], stream_));
-      if (nPS_) primal_slice_step<T><<<(unsigned)nPS_, kThreads, 0, stream_>>>(A, i);
+      if (nPS_) launch_slices(false, A, i);
       if (timed) HIPCHECK(hipEventRecord(e[1], stream_));
       primal_step<T><<<(unsigned)nP_, kThreads, 0, stream_>>>(A, i);
       if (timed) HIPCHECK(hipEventRecord(e[2], stream_));
-      if (nDS_) dual_slice_step<T><<<(unsigned)nDS_, kThreads, 0, stream_>>>(A, i);
+      if (nDS_) launch_slices(true, A, i);
       if (timed) HIPCHECK(hipEventRecord(e[3], stream_));
       dual_step<T><<<(unsigned)nD_, kThreads, 0, stream_>>>(A, i);
       if (timed) {

@@ -21,8 +21,8 @@ constexpr int kNAcc = 12;            // sums kept from a check step for the foll
 // bandwidth, bound these products, and smaller tiles keep more independent
 // gathers in flight).  Rows longer than a tile get a block of their own.
 constexpr int kPlainNB = 1024;
-constexpr int kSliceNB = 512;
-constexpr int kSliceRows = 128;  // rows per sliced row group
+constexpr int kSliceNB = 512;    // default entries per slice tile (also 256 and 1024 compiled)
+constexpr int kSliceRows = 128;  // default rows per sliced row group
 template <class T> struct Tile { static constexpr int NB = kPlainNB; };
 
 enum Mode : int { M_SKIP = 0, M_NORMAL = 1, M_CHECK = 2, M_EVAL = 3, M_RESID = 4 };

@@ -429,9 +429,9 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
 // spart for the step kernel of the same step to add up).  dual = 1: rows of
 // K gathering xbar (or xT, cx1, cx2 at an eval step); dual = 0: rows of K^T
 // gathering y (or yT, cy1, cy2).
-template <class T, bool dual>
+template <class T, bool dual, int NB>
 __device__ __forceinline__ void slice_body(const IterArgs<T>& A, int step) {
-  __shared__ T s_prod[kSliceNB];
+  __shared__ T s_prod[NB];
   __shared__ T s_rsum[3][kMaxRows];
   __shared__ int s_rp[kMaxRows + 1];
   __shared__ double s_red[kThreads / 64][kNS];
@@ -440,10 +440,10 @@ __device__ __forceinline__ void slice_body(const IterArgs<T>& A, int step) {
   const int32_t* rp = (dual ? A.brpK : A.brpKT) + b.rp_off;
   const int32_t* ci = dual ? A.K_ci : A.KT_ci;
   const T* val = dual ? A.K_v : A.KT_v;
-  TileRegs<T, kSliceNB> R;
-  load_tile<T, kSliceNB>(b, rp, ci, val, R);
+  TileRegs<T, NB> R;
+  load_tile<T, NB>(b, rp, ci, val, R);
   const T* src = dual ? A.xbar : A.y;
-  spec_products<T, kSliceNB>(b, src, R);
+  spec_products<T, NB>(b, src, R);
   const InstState& S = A.st[b.inst];
   const int64_t g = *A.gbase + step;
   const int mode = step_mode(S, g);
@@ -452,10 +452,10 @@ __device__ __forceinline__ void slice_body(const IterArgs<T>& A, int step) {
   const int64_t space = dual ? A.MS : A.NS;
   const int nv = mode == M_EVAL ? 3 : 1;
   if (mode == M_EVAL) {
-    if (dual) block_spmv_regs<T, 3, kSliceNB>(b, ci, val, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
-    else block_spmv_regs<T, 3, kSliceNB>(b, ci, val, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
+    if (dual) block_spmv_regs<T, 3, NB>(b, ci, val, R, A.xT, A.cx1, A.cx2, s_prod, s_rsum, s_rp, s_red);
+    else block_spmv_regs<T, 3, NB>(b, ci, val, R, A.yT, A.cy1, A.cy2, s_prod, s_rsum, s_rp, s_red);
   } else {
-    block_spmv1<T, kSliceNB>(b, ci, val, R, src, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
+    block_spmv1<T, NB>(b, ci, val, R, src, s_prod, s_rsum[0], s_rp, s_red, (T)1, true);
   }
   const int nrows = b.r1 - b.r0;
   const int sl = blk_slice(b);
@@ -463,14 +463,16 @@ __device__ __forceinline__ void slice_body(const IterArgs<T>& A, int step) {
     for (int a = 0; a < nv; ++a) spart[(int64_t)(a * kSlices + sl) * space + b.r0 + r] = s_rsum[a][r];
 }
 
-template <class T>
+// NB: entries per slice tile (kSliceTiles lists the compiled sizes; the
+// engine picks one per solver, and the tuner in the Python package times them)
+template <class T, int NB>
 __global__ __launch_bounds__(kThreads) void primal_slice_step(IterArgs<T> A, int step) {
-  slice_body<T, false>(A, step);
+  slice_body<T, false, NB>(A, step);
 }
 
-template <class T>
+template <class T, int NB>
 __global__ __launch_bounds__(kThreads) void dual_slice_step(IterArgs<T> A, int step) {
-  slice_body<T, true>(A, step);
+  slice_body<T, true, NB>(A, step);
 }
 
 // ---------------------------------------------------------------------------
@@ -1219,10 +1221,18 @@ template __global__ void primal_step<double>(IterArgs<double>, int);
 template __global__ void primal_step<float>(IterArgs<float>, int);
 template __global__ void dual_step<double>(IterArgs<double>, int);
 template __global__ void dual_step<float>(IterArgs<float>, int);
-template __global__ void primal_slice_step<double>(IterArgs<double>, int);
-template __global__ void primal_slice_step<float>(IterArgs<float>, int);
-template __global__ void dual_slice_step<double>(IterArgs<double>, int);
-template __global__ void dual_slice_step<float>(IterArgs<float>, int);
+template __global__ void primal_slice_step<double, 256>(IterArgs<double>, int);
+template __global__ void primal_slice_step<double, 512>(IterArgs<double>, int);
+template __global__ void primal_slice_step<double, 1024>(IterArgs<double>, int);
+template __global__ void primal_slice_step<float, 256>(IterArgs<float>, int);
+template __global__ void primal_slice_step<float, 512>(IterArgs<float>, int);
+template __global__ void primal_slice_step<float, 1024>(IterArgs<float>, int);
+template __global__ void dual_slice_step<double, 256>(IterArgs<double>, int);
+template __global__ void dual_slice_step<double, 512>(IterArgs<double>, int);
+template __global__ void dual_slice_step<double, 1024>(IterArgs<double>, int);
+template __global__ void dual_slice_step<float, 256>(IterArgs<float>, int);
+template __global__ void dual_slice_step<float, 512>(IterArgs<float>, int);
+template __global__ void dual_slice_step<float, 1024>(IterArgs<float>, int);
 template __global__ void cast_kernel<float>(const double*, float*, int64_t);
 template __global__ void scale_primal_kernel<double>(const Blk*, const double*, const double*,
                                                      const double*, const double*, double*, double*,

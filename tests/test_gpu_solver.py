@@ -542,3 +542,30 @@ def test_activity_diagnostics_match_oracle(name, code, seed):
     ref = oracle.solve(lp, oracle.Options(method=name, tol=1e-10))
     assert res["iters"] == ref.iters
     assert res["ident_iters"] == ref.ident_iters and res["active_changes"] == ref.active_changes
+
+
+
+@pytest.mark.parametrize("shape", [dict(tile_rows=128, slice_entries=256, slice_rows=64),
+                                   dict(tile_rows=37, slice_entries=1024, slice_rows=200)])
+def test_tile_shapes_trajectory_parity(shape):
+    """Other SpMV tile shapes (the tuner's search space) change only the
+    rounding order inside rows: iterates still agree with the oracle."""
+    lp = lpgen.scaled_powerlaw(21, 500, 1800)
+    print(f"case tile shape {shape}", flush=True)
+    res, x, y, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=0, **shape)
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=1000))
+    assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
+    assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
+
+
+def test_autotune_picks_a_measured_shape():
+    from paper_2407_16144_amd import autotune
+    lp = lpgen.scaled_powerlaw(21, 500, 1800)
+    print("case autotune", flush=True)
+    best, table, secs = autotune.autotune(lp, iters=256, slice_min_bytes=0)
+    assert len(table) == 2 + len(autotune.SLICE_SHAPES) - 1
+    assert best in [shape for shape, _ in table] or {**best, "slice_entries": 512, "slice_rows": 128} in \
+        [{**shape, "slice_entries": 512, "slice_rows": 128} for shape, _ in table]
+    assert all(ms > 0 for _, ms in table)
+    r, x, y, _ = _gpu(lp, 1e-6, 100_000, slice_min_bytes=0, **best)
+    assert r["status"] == halp.LP_OPTIMAL
