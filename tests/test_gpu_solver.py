@@ -564,8 +564,7 @@ def test_autotune_picks_a_measured_shape():
     print("case autotune", flush=True)
     best, table, secs = autotune.autotune(lp, iters=256, slice_min_bytes=0)
     assert len(table) == 2 + len(autotune.SLICE_SHAPES) - 1
-    assert best in [shape for shape, _ in table] or {**best, "slice_entries": 512, "slice_rows": 128} in \
-        [{**shape, "slice_entries": 512, "slice_rows": 128} for shape, _ in table]
+    assert best in [shape for shape, _ in table]
     assert all(ms > 0 for _, ms in table)
-    r, x, y, _ = _gpu(lp, 1e-6, 100_000, slice_min_bytes=0, **best)
+    r, x, y, _ = _gpu(lp, 1e-4, 100_000, slice_min_bytes=0, **best)
     assert r["status"] == halp.LP_OPTIMAL
