@@ -117,6 +117,45 @@ def cpu_baseline(lp, eta, gpu_iters, gpu_power_iters, method, budget_s=30.0):
             "seconds_per_iteration": t_iter}
 
 
+def _oracle_rate_worker(args):
+    """One LP of a pool baseline: oracle time per iteration (65 iterations
+    after scaling and a 10-step power iteration), for extrapolation."""
+    lp, method, gpu_iters, gpu_pw = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import oracle
+    from oracle import core
+    t0 = time.perf_counter()
+    P = core.scaled_problem(lp)
+    t_scale = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.power_iteration(P.K, 0, max_iters=10, min_iters=10, rtol=0.0)
+    t_pw = (time.perf_counter() - t0) / 10.0
+    t0 = time.perf_counter()
+    r = oracle.solve(lp, oracle.Options(method=method, tol=0.0, max_iter=64, eta=0.5))
+    t_iter = max(time.perf_counter() - t0 - t_scale, 1e-9) / r.iters
+    return t_scale + gpu_pw * t_pw + gpu_iters * t_iter
+
+
+def cpu_pool_baseline(lps, results, method, sample=16):
+    """The oracle on a pool of host processes (one LP at a time each), timed
+    on the first `sample` LPs and extrapolated to the GPU's per-LP iteration
+    and power-iteration counts: LPs/s = pool size / mean seconds per LP."""
+    import multiprocessing as mp
+    k = min(sample, len(lps))
+    procs = max(1, min(os.cpu_count() or 1, 16, k))
+    jobs = [(lps[i], method, results[i]["iters"], results[i]["power_iters"]) for i in range(k)]
+    t0 = time.perf_counter()
+    # fresh interpreters: the children import only the oracle (no GPU state is forked)
+    with mp.get_context("spawn").Pool(procs) as pool:
+        est = pool.map(_oracle_rate_worker, jobs)
+    wall = time.perf_counter() - t0
+    mean = sum(est) / len(est)
+    return {"value": procs / mean, "unit": "LPs/s", "cores": procs, "kind": "oracle",
+            "sample": (f"first {k} LPs, {procs} processes: scaling + 10 power iterations + 65 "
+                       f"iterations each ({wall:.1f}s), extrapolated to the GPU's iteration counts; "
+                       f"mean {mean:.1f}s per LP")}
+
+
 def _opts(halp, args, **kw):
     return halp.lp_default_options(
         method=METHODS[args.method],
@@ -208,6 +247,8 @@ def run_batch(args):
         sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)
         out["serial_fp64_rhpdhg"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
                                      "value": round(sv / sw, 3), "unit": "LPs/s"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_pool_baseline(lps, res, args.method)
     del keep
     return out
 
@@ -276,6 +317,8 @@ def run_serve(args):
         sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)
         out["serial_fp64_rhpdhg"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
                                      "value": round(sv / sw, 3), "unit": "LPs/s"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_pool_baseline(lps, [done[i][0] for i in range(len(trace))], args.method)
     return out
 
 
@@ -415,7 +458,9 @@ def main():
     achieved = byname[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     tstep = sum(avg.values())
     wl_key = f"{args.workload}-{args.precision}" if args.workload != "mps" else None
-    tr = measured_traffic(wl_key, names[dom] + ("<double>" if s == 8 else "<float>")) if wl_key else None
+    ty = "double" if s == 8 else "float"
+    kname = (f"{names[dom]}<{ty}, {opt.slice_entries}>" if "slice" in dom else f"{names[dom]}<{ty}>")
+    tr = measured_traffic(wl_key, kname) if wl_key else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
                 "kernel": names[dom], "bytes_per_launch": int(byname[dom]),
