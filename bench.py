@@ -192,7 +192,8 @@ def run_batch(args):
           flush=True)
     arr, keep = halp.make_problems(lps, on_device=True)
     torch.cuda.synchronize()
-    opt = _opts(halp, args, profile=args.profile_every, verbose=args.verbose)
+    opt = _opts(halp, args, profile=args.profile_every, verbose=args.verbose,
+                use_graph=0 if args.no_graph else 1)
     stream = torch.cuda.current_stream().cuda_stream
 
     def step():
