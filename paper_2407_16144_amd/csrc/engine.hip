@@ -1295,6 +1295,7 @@ void Engine<T>::launch_chunk() {
         HIPCHECK(hipEventRecord(e[4], stream_));
         HIPCHECK(hipEventRecord(e[5], stream_));  // empty pair: the events' own cost
       }
+      control_kernel<<<(unsigned)nslots_, kThreads, 0, stream_>>>(d_st, partP, partD, d_gbase, i, d_status);
     }
   };
   if (prof) {

@@ -604,8 +604,6 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
   __shared__ int s_rp[kMaxRows + 1];
   __shared__ double s_red[kThreads / 64][kNS];
   __shared__ double s_out[kNS];
-  __shared__ double s_sum[2][kNS];
-  __shared__ int s_last;
 
   const Blk b = A.schedD[blockIdx.x];
   if (blk_kind(b) == BK_PAD) return;
@@ -717,22 +715,26 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
 
   block_sum_ns(ps, s_red, s_out);
   if (t < kNS) A.partD[(int64_t)b.gid * kNS + t] = s_out[t];
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    const int nb = S.db1 - S.db0;
-    const int prev = __hip_atomic_fetch_add(&A.cnt[b.inst], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == nb - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  sum_partials(A.partP + (int64_t)S.pb0 * kNS, S.pb1 - S.pb0, s_red, s_sum[0]);
-  sum_partials(A.partD + (int64_t)S.db0 * kNS, S.db1 - S.db0, s_red, s_sum[1]);
-  if (t == 0) {
-    controller(A.st[b.inst], s_sum[0], s_sum[1], mode, g, A.status_out, b.inst);
-    A.cnt[b.inst] = 0;
-  }
+}
+
+// Per-LP control after a step (one workgroup per LP slot): at check, eval
+// and residual steps, the fixed-order sums of the step kernels' per-workgroup
+// partial sums, then the controller.  A kernel of its own, so that the
+// partial sums of every XCD are visible without device-scope fences inside
+// the step kernels (each of which would write back the XCD's L2).
+__global__ __launch_bounds__(kThreads) void control_kernel(InstState* st, const double* partP,
+                                                           const double* partD, const int64_t* gbase,
+                                                           int step, int* status_out) {
+  __shared__ double s_red[kThreads / 64][kNS];
+  __shared__ double s_sum[2][kNS];
+  const int inst = blockIdx.x;
+  InstState& S = st[inst];
+  const int64_t g = *gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP || mode == M_NORMAL) return;
+  sum_partials(partP + (int64_t)S.pb0 * kNS, S.pb1 - S.pb0, s_red, s_sum[0]);
+  sum_partials(partD + (int64_t)S.db0 * kNS, S.db1 - S.db0, s_red, s_sum[1]);
+  if (threadIdx.x == 0) controller(S, s_sum[0], s_sum[1], mode, g, status_out, inst);
 }
 
 __global__ void tick_kernel(int64_t* gbase, int64_t add) {
