@@ -312,6 +312,8 @@ def run_serve(args):
                       "method": args.method, "precision": args.precision,
                       "p50_latency_s": round(_pct(lat, 0.5), 4), "p99_latency_s": round(_pct(lat, 0.99), 4),
                       "solved": solved, "requests": len(trace),
+                      "seconds_to_95pct_done": round(sorted(done[i][1] for i in range(len(trace)))[
+                          max(0, math.ceil(0.95 * len(trace)) - 1)] - arrivals[0], 2),
                       "status_by_kind": {k: {str(s): v.count(s) for s in set(v)} for k, v in kinds.items()}}}
     if args.serial_baseline:
         k = min(args.serial_baseline, len(lps))
