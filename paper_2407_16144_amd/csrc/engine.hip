@@ -375,6 +375,9 @@ void Engine<T>::allocate() {
   HIPCHECK(hipMemsetAsync(d_cnt, 0, sizeof(int) * nslots_, stream_));
   HIPCHECK(hipMemsetAsync(d_status, 0, sizeof(int) * nslots_, stream_));
   HIPCHECK(hipMemsetAsync(d_st, 0, sizeof(InstState) * nslots_, stream_));
+  // a zeroed state reads as running: park every slot until an LP is added
+  set_limit_status_kernel<<<nblk(nslots_), 256, 0, stream_>>>(d_st, d_status, nslots_, ST_ITER_LIMIT);
+  HIPCHECK(hipGetLastError());
   const int64_t gb = -(int64_t)opt_.chunk;
   HIPCHECK(hipMemcpyAsync(d_gbase, &gb, sizeof(int64_t), hipMemcpyHostToDevice, stream_));
   for (int i = 0; i < 2; ++i) {
