@@ -173,9 +173,12 @@ def serial_solve(halp, lps, tol, max_iter):
     opt = halp.lp_default_options(method=halp.LP_METHOD_RHPDHG)
     t0 = time.perf_counter()
     solved = 0
-    for lp in lps:
+    for i, lp in enumerate(lps):
         r, *_ = halp.solve_lp(lp, tol=tol, max_iter=max_iter, opt=opt, on_device=True)
         solved += r["status"] in (1, 2, 3)
+        if (i + 1) % 16 == 0 or i + 1 == len(lps):
+            print(f"serial FP64: {i + 1}/{len(lps)} LPs, {solved} solved, "
+                  f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     return solved, time.perf_counter() - t0
 
 
