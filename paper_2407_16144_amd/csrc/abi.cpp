@@ -744,9 +744,11 @@ int lp_server_submit(lp_server* s, const lp_problem* p, double tol, int64_t max_
     r.tol = tol;
     r.max_iter = max_iter;
     r.t_arrival = t_arrival;
-    if (s->eng->live() == 0 && !s->eng->fits(r.n, m, nnz))
+    // refused at once if it would not fit even an idle server (it would
+    // otherwise block the head of the queue for good)
+    if (!s->eng->fits_empty(r.n, m, nnz))
       return fail(LP_ERR_INVALID, "LP is larger than the server's reserved memory");
-    if (s->eng64 && tol < s->opt.polish_tol && s->eng64->live() == 0 && !s->eng64->fits(r.n, m, nnz))
+    if (s->eng64 && tol < s->opt.polish_tol && !s->eng64->fits_empty(r.n, m, nnz))
       return fail(LP_ERR_INVALID, "LP is larger than the server's reserved memory (FP64 phase)");
     *ticket = r.ticket;
     s->queue.push_back(r.ticket);

@@ -115,7 +115,9 @@ class EngineBase {
   virtual hipStream_t stream() const = 0;
   // bytes of device storage an LP of this size needs (admission control)
   virtual int64_t footprint(int64_t n, int64_t m, int64_t nnz) const = 0;
+  // fits: room for the LP now; fits_empty: room once no LP is live
   virtual bool fits(int64_t n, int64_t m, int64_t nnz) const = 0;
+  virtual bool fits_empty(int64_t n, int64_t m, int64_t nnz) const = 0;
   virtual KernelTimes kernel_times() const = 0;
   // last check candidate T(z) in the scaled space, as float64 device arrays
   virtual void export_point(int id, double* x, double* y, double* omega) = 0;

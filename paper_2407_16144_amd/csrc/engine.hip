@@ -259,6 +259,9 @@ class Engine final : public EngineBase {
     for (auto& s : slots_) free_slots += !s.used;
     return free_slots > 0 && am_.can(m + 1) && an_.can(n + 1) && az_.can(nnz);
   }
+  bool fits_empty(int64_t n, int64_t m, int64_t nnz) const override {
+    return nslots_ > 0 && m + 1 <= MS_ && n + 1 <= NS_ && nnz <= NZ_;
+  }
 
   std::vector<int> add(const std::vector<Problem>& probs, bool on_device, bool partial) override;
   void set_params(const std::vector<int>& ids, double tol, int64_t max_iter,

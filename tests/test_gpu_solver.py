@@ -512,6 +512,31 @@ def test_server_results_equal_single_results(prec, graph):
             assert kkt <= 1e-6 * (1 + 1e-6), parts
 
 
+def test_server_refuses_lp_larger_than_its_memory():
+    """An LP that would not fit even an idle server is refused at submit
+    time, also while other LPs are live (queued, it would block the head of
+    the queue for good); the live LP still finishes."""
+    print("case server capacity", flush=True)
+    h = halp.lp_server_create(2_000_000, 3, opt=halp.lp_default_options())
+    try:
+        small = lpgen.scaled_powerlaw(5, 50, 150)
+        t = halp.lp_server_submit(h, small, 1e-6, 200_000, 0.0)
+        halp.lp_server_step(h, 1)
+        assert halp.lp_server_info(h)[1] == 1
+        big = lpgen.scaled_powerlaw(6, 2000, 6000)
+        with pytest.raises(halp.HalpError, match="larger than"):
+            halp.lp_server_submit(h, big, 1e-6, 200_000, 1.0)
+        for _ in range(10_000):
+            r, _ = halp.lp_server_poll(h, t)
+            if r is not None:
+                break
+            halp.lp_server_step(h, 4)
+        assert r is not None and r.as_dict()["status"] == halp.LP_OPTIMAL
+        assert halp.lp_server_info(h)[0] == 0
+    finally:
+        halp.lp_server_destroy(h)
+
+
 def test_mps_model_solves():
     """An LP read from MPS (maximisation, ranged row, objective constant) is
     solved to the optimum HiGHS finds for the same model typed in directly."""
