@@ -36,14 +36,15 @@ def algorithmic_bytes(n, m, nnz, s):
     return primal, dual
 
 
-def kernel_bytes(n, m, nnz, s, primal_sliced, dual_sliced):
+def kernel_bytes(n, m, nnz, s, primal_sliced, dual_sliced, dual_sorted=False):
     """Algorithmic bytes per launch of each of the four kernels of a plain
     step.  Where a product is column-sliced, its slice kernel is charged the
     matrix, row pointers and gathered vector, and the step kernel only its
     epilogue; the slice partial sums exchanged between the two are not
-    algorithmic traffic and are charged to neither."""
+    algorithmic traffic and are charged to neither.  Column-sorted slices of
+    K carry no row pointers (the row is packed into the column index)."""
     pmat = nnz * (s + 4) + 4 * (n + 1) + s * m
-    dmat = nnz * (s + 4) + 4 * (m + 1) + s * n
+    dmat = nnz * (s + 4) + s * n + (0 if dual_sliced and dual_sorted else 4 * (m + 1))
     pepi, depi = 7 * s * n, 4 * s * m
     return {"primal_slice": pmat if primal_sliced else 0,
             "primal_step": pepi + (0 if primal_sliced else pmat),
@@ -455,9 +456,10 @@ def main():
     avg = {k: max(ksum[k + "_ms"] / kn - ev, 0.0) if ksum[k + "_ms"] > 0 else 0.0
            for k in ("primal_slice", "primal", "dual_slice", "dual")}
     primal_sliced, dual_sliced = avg["primal_slice"] > 0, avg["dual_slice"] > 0
-    kb = kernel_bytes(lp.n, lp.m, lp.nnz, s, primal_sliced, dual_sliced)
+    kb = kernel_bytes(lp.n, lp.m, lp.nnz, s, primal_sliced, dual_sliced, opt.slice_sort == 1)
     names = {"primal_slice": "primal_slice_step", "primal": "primal_step",
-             "dual_slice": "dual_slice_step", "dual": "dual_step"}
+             "dual_slice": "dual_sorted_slice_step" if opt.slice_sort == 1 else "dual_slice_step",
+             "dual": "dual_step"}
     byname = {"primal_slice": kb["primal_slice"], "primal": kb["primal_step"],
               "dual_slice": kb["dual_slice"], "dual": kb["dual_step"]}
     dom = max(avg, key=lambda k: avg[k])
@@ -465,7 +467,8 @@ def main():
     tstep = sum(avg.values())
     wl_key = f"{args.workload}-{args.precision}" if args.workload != "mps" else None
     ty = "double" if s == 8 else "float"
-    kname = (f"{names[dom]}<{ty}, {opt.slice_entries}>" if "slice" in dom else f"{names[dom]}<{ty}>")
+    kname = (f"{names[dom]}<{ty}, {opt.slice_entries}>" if names[dom] in ("primal_slice_step", "dual_slice_step")
+             else f"{names[dom]}<{ty}>")
     tr = measured_traffic(wl_key, kname) if wl_key else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,

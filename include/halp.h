@@ -134,6 +134,14 @@ typedef struct {
                                off into their own strided tiles) */
   int slice_entries;        /* entries per column-slice tile: 256, 512 (default) or 1024 */
   int slice_rows;           /* rows per sliced row group, 1..256 (default 128) */
+  int slice_sort;           /* sliced K (dual product): 1 (default) stores each slice tile's
+                               entries in column order, sort_rows rows per tile, and adds
+                               the products into the row sums with LDS atomics (faster;
+                               the order of the additions within a row, and so the last
+                               bits of the iterates, may differ from run to run); 0: rows in
+                               order with fixed-order sums (slice_entries, slice_rows) */
+  int sort_rows;            /* rows per column-sorted slice tile, 1..4096 (default 4096;
+                               fewer when the slice is wider than 2^(32 - log2 rows)) */
 } lp_options;
 
 typedef struct {

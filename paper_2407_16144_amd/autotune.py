@@ -7,11 +7,13 @@ once per candidate shape, runs a fixed number of steps with every chunk
 timed by HIP events (their own cost taken out), and returns the shape with
 the least kernel time per step.
 
-Search (coordinate descent, 2 + 6 candidates):
+Search (coordinate descent, 2 + 8 candidates):
   1. tile_rows in {128, 256}: rows per plain workgroup tile (Kᵀ of the large
-     LP, every product of small LPs);
-  2. only if the LP has a column-sliced product: slice_entries in
-     {256, 512, 1024} x slice_rows in {64, 128}, with the best tile_rows.
+     LP, every product of small LPs), with the default slices;
+  2. only if the LP has a column-sliced product, with the best tile_rows:
+     column-sorted slices of K with sort_rows in {1024, 2048} (4096, the
+     default, was timed in step 1), and fixed-order slices (slice_sort 0)
+     with slice_entries in {256, 512, 1024} x slice_rows in {64, 128}.
 
 Each candidate's solve starts from scratch and its iterates are discarded;
 the chosen options are then passed to the real solve.
@@ -25,6 +27,7 @@ from . import (lp_create, lp_default_options, lp_destroy, lp_kernel_times, lp_so
                lp_batch_destroy)
 
 TILE_ROWS = (128, 256)
+SORT_ROWS = (1024, 2048)
 SLICE_SHAPES = tuple((e, r) for e in (256, 512, 1024) for r in (64, 128))
 
 
@@ -88,10 +91,9 @@ def autotune(lp_or_lps, iters: int = 640, stream=None, **base):
         if ms < best_ms:
             best, best_ms = {"tile_rows": r}, ms
     if sliced:
-        for e, r in SLICE_SHAPES:
-            shape = {**best, "slice_entries": e, "slice_rows": r}
-            if shape == {**best, "slice_entries": 512, "slice_rows": 128}:
-                continue  # the default slice shape was timed in step 1
+        cands = [{**best, "slice_sort": 1, "sort_rows": r} for r in SORT_ROWS]
+        cands += [{**best, "slice_sort": 0, "slice_entries": e, "slice_rows": r} for e, r in SLICE_SHAPES]
+        for shape in cands:
             ms, _ = measure(shape)
             if ms < best_ms:
                 best, best_ms = shape, ms

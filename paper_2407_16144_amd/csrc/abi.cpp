@@ -70,6 +70,8 @@ halp::Options to_opts(const lp_options* o) {
   r.tile_rows = o->tile_rows;
   r.slice_entries = o->slice_entries;
   r.slice_rows = o->slice_rows;
+  r.slice_sort = o->slice_sort;
+  r.sort_rows = o->sort_rows;
   return r;
 }
 
@@ -79,6 +81,9 @@ void check_opts(const halp::Options& o) {
     throw halp::Error(LP_ERR_INVALID, "tile_rows and slice_rows must be in 1..256");
   if (o.slice_entries != 256 && o.slice_entries != 512 && o.slice_entries != 1024)
     throw halp::Error(LP_ERR_INVALID, "slice_entries must be 256, 512 or 1024");
+  if (o.slice_sort < 0 || o.slice_sort > 1) throw halp::Error(LP_ERR_INVALID, "slice_sort must be 0 or 1");
+  if (o.sort_rows < 1 || o.sort_rows > halp::kSortRows)
+    throw halp::Error(LP_ERR_INVALID, "sort_rows must be in 1..4096");
   if (o.restart_mode == 1 && o.fixed_restart_len < 1)
     throw halp::Error(LP_ERR_INVALID, "fixed restarts need fixed_restart_len >= 1");
   if (o.method < 0 || o.method > 2) throw halp::Error(LP_ERR_INVALID, "method must be 0, 1 or 2");
@@ -388,6 +393,8 @@ void lp_default_options(lp_options* o) {
   o->tile_rows = d.tile_rows;
   o->slice_entries = d.slice_entries;
   o->slice_rows = d.slice_rows;
+  o->slice_sort = d.slice_sort;
+  o->sort_rows = d.sort_rows;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }
@@ -757,6 +764,8 @@ int lp_server_submit(lp_server* s, const lp_problem* p, double tol, int64_t max_
   });
 }
 
+}  // extern "C"
+
 namespace {
 
 void finish_request(lp_server* s, Request& r, halp::EngineBase& eng, int slot, const lp_result& res, double tnow) {
@@ -794,6 +803,8 @@ std::vector<std::pair<int64_t, int>> admit(lp_server* s, halp::EngineBase& eng, 
 }
 
 }  // namespace
+
+extern "C" {
 
 int lp_server_step(lp_server* s, int chunks, int* n_done) {
   return guarded([&]() -> int {

@@ -292,6 +292,7 @@ class Engine final : public EngineBase {
   void preprocess(const std::vector<int>& ids, const std::vector<Blk>& nP, const std::vector<Blk>& nD,
                   const std::vector<int4>& nr);
   void slice_matrix(int id, bool dual);
+  void slice_sorted(int id);
   IterArgs<T> args() const;
   void pull_states();
 
@@ -988,6 +989,10 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
 // (slices over its constraints) into the column-sliced layout.
 template <class T>
 void Engine<T>::slice_matrix(int id, bool dual) {
+  if (dual && opt_.slice_sort) {
+    slice_sorted(id);
+    return;
+  }
   const int NB = opt_.slice_entries;
   Slot& S = slots_[id];
   const int64_t nrows = dual ? S.m : S.n;
@@ -1057,6 +1062,145 @@ void Engine<T>::slice_matrix(int id, bool dual) {
   // slice partial sums live in space-sized buffers, allocated on first use
   if (dual && !spartD) dalloc(&spartD, 3 * kSlices * MS_);
   if (!dual && !spartP) dalloc(&spartP, 3 * kSlices * NS_);
+}
+
+// Column-sorted slicing of one LP's K (the dual product's gathers): row
+// groups of at most sort_rows rows and kSortEntries entries per slice; the
+// entries of each (group, slice) block in column order, each column index
+// packed with the entry's row in the group (see blk_rowbits).  Built on the
+// device: keys in row-major block order, a segmented radix sort of the keys
+// within each block (keys are unique in a block, so the order is fixed), and
+// a gather of the values.
+template <class T>
+void Engine<T>::slice_sorted(int id) {
+  Slot& S = slots_[id];
+  const int64_t nrows = S.m, r0 = S.row0, c0 = S.col0, len = S.n;
+  if (nrows == 0 || S.nnz == 0) return;
+  // bits of a column offset within the widest slice, bits of a row in a group
+  int64_t wmax = 0;
+  for (int q = 0; q < kSlices; ++q) {
+    const int64_t a = (q * len + kSlices - 1) / kSlices, b = ((q + 1) * len + kSlices - 1) / kSlices;
+    wmax = std::max(wmax, b - a);
+  }
+  int cb = 0;
+  while (((int64_t)1 << cb) < wmax) ++cb;
+  int64_t rows = std::min<int64_t>(opt_.sort_rows, kSortRows);
+  if (cb >= 32) throw Error(-1, "LP too wide for sorted slices");
+  rows = std::min<int64_t>(rows, (int64_t)1 << (32 - cb));
+  int rb = 0;
+  while (((int64_t)1 << rb) < rows) ++rb;
+  int32_t* d_cnt = nullptr;
+  dalloc(&d_cnt, nrows * kSlices);
+  slice_count_kernel<<<nblk(nrows), 256, 0, stream_>>>(K_rp, K_ci, r0, nrows, c0, len, d_cnt);
+  std::vector<int32_t> cnt(nrows * kSlices);
+  HIPCHECK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  dfree(d_cnt);
+  // groups
+  std::vector<std::pair<int64_t, int64_t>> groups;
+  int64_t start = 0;
+  int64_t acc[kSlices] = {0};
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int32_t* c = cnt.data() + r * kSlices;
+    bool over = (r - start) >= rows;
+    for (int q = 0; q < kSlices; ++q) over |= acc[q] + c[q] > kSortEntries;
+    if (over && r > start) {
+      groups.emplace_back(start, r);
+      start = r;
+      for (int q = 0; q < kSlices; ++q) acc[q] = 0;
+    }
+    for (int q = 0; q < kSlices; ++q) acc[q] += c[q];
+  }
+  groups.emplace_back(start, nrows);
+  // blocks, row-major positions and the row of each row in its group
+  std::vector<Blk> grp, sl;
+  for (int64_t a = 0; a < nrows; a += kMaxRows) {
+    Blk ep;
+    ep.r0 = (int32_t)(r0 + a);
+    ep.r1 = (int32_t)(r0 + std::min<int64_t>(a + kMaxRows, nrows));
+    ep.inst = id;
+    ep.meta = blk_meta(BK_STREAM, kSlices, 0);
+    ep.gid = (int32_t)grp.size();
+    ep.rp_off = 0;
+    ep.p0 = 0;
+    ep.pn = 0;
+    grp.push_back(ep);
+  }
+  std::vector<int32_t> dst(nrows * kSlices), rloc(nrows), off;
+  int64_t pos = S.nz0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const int64_t a = groups[g].first, e = groups[g].second;
+    for (int64_t r = a; r < e; ++r) rloc[r] = (int32_t)(r - a);
+    for (int q = 0; q < kSlices; ++q) {
+      Blk k;
+      k.r0 = (int32_t)(r0 + a);
+      k.r1 = (int32_t)(r0 + e);
+      k.inst = id;
+      k.gid = (int32_t)g;
+      k.rp_off = (int32_t)(c0 + (q * len + kSlices - 1) / kSlices);
+      k.p0 = (int32_t)pos;
+      off.push_back((int32_t)(pos - S.nz0));
+      for (int64_t r = a; r < e; ++r) {
+        dst[r * kSlices + q] = (int32_t)pos;
+        pos += cnt[r * kSlices + q];
+      }
+      k.pn = (int32_t)(pos - k.p0);
+      k.meta = blk_meta(BK_STREAM, kSlices, q) | (rb << 25);
+      sl.push_back(k);
+    }
+  }
+  off.push_back((int32_t)(pos - S.nz0));
+  if (pos != S.nz0 + S.nnz) throw Error(-3, "sorted slice layout does not cover the matrix");
+  const int64_t nnz = S.nnz;
+  int32_t *d_dst = nullptr, *d_rloc = nullptr, *d_off = nullptr, *src_in = nullptr, *src_out = nullptr;
+  uint32_t *key_in = nullptr, *key_out = nullptr;
+  T* v2 = nullptr;
+  double* v642 = nullptr;
+  dalloc(&d_dst, nrows * kSlices);
+  dalloc(&d_rloc, nrows);
+  dalloc(&d_off, (int64_t)off.size());
+  dalloc(&key_in, nnz);
+  dalloc(&key_out, nnz);
+  dalloc(&src_in, nnz);
+  dalloc(&src_out, nnz);
+  dalloc(&v2, nnz);
+  if (sizeof(T) != 8) dalloc(&v642, nnz);
+  HIPCHECK(hipMemcpyAsync(d_dst, dst.data(), sizeof(int32_t) * dst.size(), hipMemcpyHostToDevice, stream_));
+  HIPCHECK(hipMemcpyAsync(d_rloc, rloc.data(), sizeof(int32_t) * rloc.size(), hipMemcpyHostToDevice, stream_));
+  HIPCHECK(hipMemcpyAsync(d_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, stream_));
+  // positions run from nz0: shift the temporaries by -nz0
+  slice_keys_kernel<<<nblk(nrows), 256, 0, stream_>>>(K_rp, K_ci, r0, nrows, c0, len, d_dst, d_rloc, rb,
+                                                      key_in - S.nz0, src_in - S.nz0);
+  HIPCHECK(hipGetLastError());
+  const int nseg = (int)sl.size();
+  size_t tmp_bytes = 0;
+  HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tmp_bytes, key_in, key_out, src_in, src_out,
+                                                       (int)nnz, nseg, d_off, d_off + 1, 0, 32, stream_));
+  void* tmp = nullptr;
+  HIPCHECK(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
+  HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, src_in, src_out,
+                                                       (int)nnz, nseg, d_off, d_off + 1, 0, 32, stream_));
+  sorted_gather_kernel<T><<<nblk(nnz), 256, 0, stream_>>>(key_out, src_out, K_v, K_v64, nnz, K_ci + S.nz0, v2,
+                                                          v642);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipMemcpyAsync(K_v + S.nz0, v2, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
+  if (v642) HIPCHECK(hipMemcpyAsync(K_v64 + S.nz0, v642, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
+  HIPCHECK(hipStreamSynchronize(stream_));
+  (void)hipFree(tmp);
+  dfree(d_dst);
+  dfree(d_rloc);
+  dfree(d_off);
+  dfree(key_in);
+  dfree(key_out);
+  dfree(src_in);
+  dfree(src_out);
+  dfree(v2);
+  dfree(v642);
+  S.bD = grp;
+  S.bDS = sl;
+  S.brpD0 = 0;
+  S.brpDn = 0;
+  if (!spartD) dalloc(&spartD, 3 * kSlices * MS_);
 }
 
 template <class T>
@@ -1253,6 +1397,10 @@ void Engine<T>::rebuild_schedules() {
 template <class T>
 void Engine<T>::launch_slices(bool dual, const IterArgs<T>& A, int step) {
   const unsigned g = (unsigned)(dual ? nDS_ : nPS_);
+  if (dual && opt_.slice_sort) {
+    dual_sorted_slice_step<T><<<g, kThreads, 0, stream_>>>(A, step);
+    return;
+  }
   switch (opt_.slice_entries) {
     case 256:
       if (dual) dual_slice_step<T, 256><<<g, kThreads, 0, stream_>>>(A, step);

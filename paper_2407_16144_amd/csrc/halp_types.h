@@ -55,6 +55,16 @@ __host__ __device__ inline int blk_nsl(const Blk& b) { return (b.meta >> 8) & 0x
 __host__ __device__ inline int blk_slice(const Blk& b) { return (b.meta >> 16) & 0xff; }
 constexpr int32_t kBlkNT = 1 << 24;
 __host__ __device__ inline bool blk_nt(const Blk& b) { return (b.meta & kBlkNT) != 0; }
+
+// Column-sorted slice blocks (dual product of a sliced K when
+// Options::slice_sort is on): the block's entries are ordered by column, and
+// each column index is stored as (column - first column of the slice) << rb
+// | (row - b.r0), with rb in meta bits 25..29 and the slice's first column
+// (a space position) in rp_off.  A sorted group has at most kSortRows rows
+// (its row sums sit in LDS) and at most kSortEntries entries per slice.
+constexpr int kSortRows = 4096;
+constexpr int kSortEntries = 1 << 16;
+__host__ __device__ inline int blk_rowbits(const Blk& b) { return (b.meta >> 25) & 31; }
 __host__ __device__ inline int32_t blk_meta(int kind, int nsl, int slice) {
   return kind | (nsl << 8) | (slice << 16);
 }

@@ -475,6 +475,67 @@ __global__ __launch_bounds__(kThreads) void dual_slice_step(IterArgs<T> A, int s
   slice_body<T, true, NB>(A, step);
 }
 
+// Row sums of one column-sorted slice block for the gathered vector src:
+// consecutive entries gather nearby elements of the slice, so the rows of
+// the group share the cache lines of their gathers.  Products go to the LDS
+// row sums s_row by atomic adds, so the order of the additions within a row
+// is not fixed (the last bits of a sum can differ from run to run).
+template <class T, bool NT>
+__device__ __forceinline__ void sorted_rows_sum(const Blk& b, const uint32_t* __restrict__ w,
+                                                const T* __restrict__ val, const T* __restrict__ src,
+                                                T* s_row) {
+  constexpr int U = 8;  // entries in flight per thread
+  const int rb = blk_rowbits(b);
+  const uint32_t rmask = (1u << rb) - 1u;
+  const T* srcb = src + b.rp_off;
+  for (int e0 = threadIdx.x; e0 < b.pn; e0 += kThreads * U) {
+    uint32_t k[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < b.pn) {
+        k[u] = ld_entry<NT>(w + b.p0 + e);
+        v[u] = ld_entry<NT>(val + b.p0 + e);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < b.pn) atomicAdd(&s_row[k[u] & rmask], v[u] * srcb[k[u] >> rb]);
+    }
+  }
+}
+
+// Partial row sums of one column slice of a sorted row group of K (written
+// to spartD for the dual step of the same step to add up), gathering xbar,
+// or xT, cx1 and cx2 one after the other at an eval step.
+template <class T>
+__global__ __launch_bounds__(kThreads) void dual_sorted_slice_step(IterArgs<T> A, int step) {
+  __shared__ T s_row[kSortRows];
+  const Blk b = A.schedDS[blockIdx.x];
+  if (blk_kind(b) == BK_PAD) return;
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP) return;
+  const int nrows = b.r1 - b.r0;
+  const int sl = blk_slice(b);
+  const int nv = mode == M_EVAL ? 3 : 1;
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(A.K_ci);
+  for (int a = 0; a < nv; ++a) {
+    const T* src = mode != M_EVAL ? A.xbar : a == 0 ? A.xT : a == 1 ? A.cx1 : A.cx2;
+    for (int r = threadIdx.x; r < nrows; r += kThreads) s_row[r] = (T)0;
+    lds_barrier();
+    if (blk_nt(b)) sorted_rows_sum<T, true>(b, w, A.K_v, src, s_row);
+    else sorted_rows_sum<T, false>(b, w, A.K_v, src, s_row);
+    lds_barrier();
+    for (int r = threadIdx.x; r < nrows; r += kThreads)
+      A.spartD[(int64_t)(a * kSlices + sl) * A.MS + b.r0 + r] = s_row[r];
+    lds_barrier();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // controller: runs once per LP per check / eval / residual step
 // ---------------------------------------------------------------------------
@@ -1105,6 +1166,41 @@ __global__ void slice_scatter_kernel(const int32_t* rp, const int32_t* ci, const
   }
 }
 
+// Sorted slicing, step 1: row r's entries go to their row-major positions
+// in the sorted groups (dst as for slice_scatter_kernel), each with its sort
+// key (column - first column of its slice) << rb | (r - first row of the
+// group) and the position it came from.
+__global__ void slice_keys_kernel(const int32_t* rp, const int32_t* ci, int64_t r0, int64_t nrows, int64_t c0,
+                                  int64_t len, const int32_t* dst, const int32_t* rloc, int rb,
+                                  uint32_t* key_out, int32_t* src_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int32_t d[kSlices];
+  for (int q = 0; q < kSlices; ++q) d[q] = dst[r * kSlices + q];
+  for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
+    const int64_t c = ci[e] - c0;
+    const int q = (int)((c * kSlices) / len);
+    const int64_t first = (q * len + kSlices - 1) / kSlices;
+    const int32_t p = d[q]++;
+    key_out[p] = ((uint32_t)(c - first) << rb) | (uint32_t)rloc[r];
+    src_out[p] = e;
+  }
+}
+
+// Sorted slicing, step 2 (after the keys are sorted within each block):
+// entry p takes the sorted key as its packed column index and the value of
+// the entry it came from.
+template <class V>
+__global__ void sorted_gather_kernel(const uint32_t* key, const int32_t* src, const V* val, const double* v64,
+                                     int64_t nnz, int32_t* ci_out, V* val_out, double* v64_out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t e = src[p];
+  ci_out[p] = (int32_t)key[p];
+  val_out[p] = val[e];
+  if (v64_out) v64_out[p] = v64[e];
+}
+
 template <class V>
 __global__ void transpose_gather_kernel(const int32_t* perm, const int32_t* rowid, const V* val,
                                         int64_t z0, int64_t nnz, int32_t* kt_ci, V* kt_val) {
@@ -1235,6 +1331,12 @@ template __global__ void dual_slice_step<double, 1024>(IterArgs<double>, int);
 template __global__ void dual_slice_step<float, 256>(IterArgs<float>, int);
 template __global__ void dual_slice_step<float, 512>(IterArgs<float>, int);
 template __global__ void dual_slice_step<float, 1024>(IterArgs<float>, int);
+template __global__ void dual_sorted_slice_step<double>(IterArgs<double>, int);
+template __global__ void dual_sorted_slice_step<float>(IterArgs<float>, int);
+template __global__ void sorted_gather_kernel<double>(const uint32_t*, const int32_t*, const double*,
+                                                      const double*, int64_t, int32_t*, double*, double*);
+template __global__ void sorted_gather_kernel<float>(const uint32_t*, const int32_t*, const float*,
+                                                     const double*, int64_t, int32_t*, float*, double*);
 template __global__ void cast_kernel<float>(const double*, float*, int64_t);
 template __global__ void scale_primal_kernel<double>(const Blk*, const double*, const double*,
                                                      const double*, const double*, double*, double*,

@@ -300,8 +300,8 @@ def test_streamed_tiles_give_identical_iterates(sliced, budget):
     lp = lpgen.scaled_powerlaw(31, 400, 1500)
     sl = 0 if sliced else -1
     print(f"case streamed tiles sliced={sliced} budget={budget}", flush=True)
-    r1, x1, y1, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=sl, cache_budget_bytes=-1)
-    r2, x2, y2, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=sl, cache_budget_bytes=budget)
+    r1, x1, y1, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=sl, cache_budget_bytes=-1, slice_sort=0)
+    r2, x2, y2, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=sl, cache_budget_bytes=budget, slice_sort=0)
     assert r1["iters"] == r2["iters"] and r1["restarts"] == r2["restarts"]
     assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
     ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=1000))
@@ -380,14 +380,16 @@ def test_iteration_limit_and_errors():
 
 # ------------------------------------------------------------------ column-sliced layout
 
+@pytest.mark.parametrize("sort", [0, 1])
 @pytest.mark.parametrize("name,code", METHODS)
-def test_sliced_layout_trajectory_parity(name, code):
+def test_sliced_layout_trajectory_parity(name, code, sort):
     """K and K^T stored column-sliced (one slice per XCD, forced on a small LP):
-    the slice partial sums are added in a fixed order, so trajectories still
-    agree with the oracle to 1e-10."""
+    the slice partial sums are added in a fixed order, and sorted slices of K
+    change only the order of the additions within a row, so trajectories
+    still agree with the oracle to 1e-10."""
     lp = lpgen.scaled_powerlaw(21, 500, 1800)
-    print(f"case sliced trajectory {name}", flush=True)
-    res, x, y, _ = _gpu(lp, 0.0, 1000, method=code, slice_min_bytes=0)
+    print(f"case sliced trajectory {name} sort={sort}", flush=True)
+    res, x, y, _ = _gpu(lp, 0.0, 1000, method=code, slice_min_bytes=0, slice_sort=sort)
     ref = oracle.solve(lp, oracle.Options(method=name, tol=0.0, max_iter=1000))
     assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
     assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
@@ -406,9 +408,11 @@ def test_sliced_layout_certificates():
     assert oracle.dual_ray_check(lp, ray)[0]
 
 
-def test_sliced_long_rows():
+@pytest.mark.parametrize("sort", [0, 1])
+def test_sliced_long_rows(sort):
     """A row whose share of one column slice exceeds a stream tile (2048
-    entries) takes the long-block path of the slice kernel."""
+    entries) takes the long-block path of the slice kernel (row-major
+    slices), or shares a sorted block with other rows (sorted slices)."""
     base = lpgen.scaled_powerlaw(9, 400, 30000)
     rng = np.random.default_rng(5)
     dense_cols = np.sort(rng.choice(base.n, 20000, replace=False)).astype(np.int32)
@@ -421,19 +425,21 @@ def test_sliced_long_rows():
     rowptr = np.concatenate([rp[:me + 1], rp[me:] + 20000]).astype(np.int32)
     rhs = np.concatenate([base.rhs[:me], [vals @ xs[dense_cols]], base.rhs[me:]])
     lp = lpgen.LP(base.n, me + 1, base.m_ineq, rowptr, col, val, base.c, rhs, base.lb, base.ub)
-    print("case sliced long row", flush=True)
+    print(f"case sliced long row sort={sort}", flush=True)
     P = core.scaled_problem(lp)
     s, _ = oracle.power_iteration(P.K, 0)
-    res, x, y, _ = _gpu(lp, 0.0, 320, eta=0.9 / s, slice_min_bytes=0)
+    res, x, y, _ = _gpu(lp, 0.0, 320, eta=0.9 / s, slice_min_bytes=0, slice_sort=sort)
     ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=320, eta=0.9 / s))
     assert res["iters"] == ref.iters
     assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
 
 
 def test_sliced_batch_equals_single():
+    """Fixed-order (row-major) slices: an LP's result does not depend on the
+    batch it is in, to the last bit."""
     lps = [lpgen.scaled_powerlaw(300 + i, m, 3 * m) for i, m in enumerate([60, 500, 20])]
     print("case sliced batch", flush=True)
-    opt = halp.lp_default_options(slice_min_bytes=0)
+    opt = halp.lp_default_options(slice_min_bytes=0, slice_sort=0)
     h = halp.lp_batch_create(lps, opt=opt)
     try:
         halp.lp_batch_solve(h, 1e-6, 100_000)
@@ -447,6 +453,48 @@ def test_sliced_batch_equals_single():
         halp.lp_batch_destroy(h)
 
 
+
+
+@pytest.mark.parametrize("sort_rows,budget", [(4096, -1), (37, 0), (300, 100_000)])
+def test_sorted_slices_match_fixed_order_slices(sort_rows, budget):
+    """Column-sorted slices of K (LDS atomic row sums; groups of sort_rows
+    rows, ragged at the end; all, none or part of the tiles streamed past the
+    cache budget) give the fixed-order slices' iterates up to the order of
+    the additions within a row."""
+    lp = lpgen.scaled_powerlaw(31, 400, 1500)
+    print(f"case sorted slices rows={sort_rows} budget={budget}", flush=True)
+    r0, x0, y0, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=0, slice_sort=0)
+    r1, x1, y1, _ = _gpu(lp, 0.0, 1000, slice_min_bytes=0, slice_sort=1, sort_rows=sort_rows,
+                         cache_budget_bytes=budget)
+    assert r1["iters"] == r0["iters"] and r1["restarts"] == r0["restarts"]
+    assert _rel(x1, x0) <= 1e-10 and _rel(y1, y0) <= 1e-10
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=1000))
+    assert _rel(x1, ref.x) <= 1e-10 and _rel(y1, ref.y) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [halp.LP_PREC_FP64, halp.LP_PREC_FP32])
+def test_sorted_slices_batch_solves(prec):
+    """A batch of sliced LPs with sorted slices (FP64, and FP32 with its FP64
+    polish): every LP is solved to the tolerance, checked in FP64 by the
+    oracle's KKT error."""
+    lps = [lpgen.scaled_powerlaw(300 + i, m, 3 * m) for i, m in enumerate([60, 500, 20])]
+    lps.append(lpgen.add_contradictory_rows(lpgen.scaled_powerlaw(9, 80, 240), seed=4))
+    print(f"case sorted sliced batch prec={prec}", flush=True)
+    opt = halp.lp_default_options(slice_min_bytes=0, slice_sort=1, precision=prec)
+    h = halp.lp_batch_create(lps, opt=opt)
+    try:
+        halp.lp_batch_solve(h, 1e-6, 200_000)
+        for i, lp in enumerate(lps):
+            rb = halp.lp_batch_status(h, i).as_dict()
+            xb, yb = halp.lp_batch_get_solution(h, i, lp.n, lp.m)
+            if i == len(lps) - 1:
+                assert rb["status"] == halp.LP_PRIMAL_INFEASIBLE
+                continue
+            assert rb["status"] == halp.LP_OPTIMAL, (i, rb)
+            kkt, parts = oracle.rel_kkt(lp, xb, yb)
+            assert kkt <= 1e-6 * (1 + 1e-6), (i, parts)
+    finally:
+        halp.lp_batch_destroy(h)
 @pytest.mark.parametrize("on_device", [False, True])
 def test_fp32_with_fp64_polish(on_device):
     """FP32 phase to the polish tolerance, then FP64 from the FP32 candidate."""
@@ -570,8 +618,10 @@ def test_activity_diagnostics_match_oracle(name, code, seed):
 
 
 
-@pytest.mark.parametrize("shape", [dict(tile_rows=128, slice_entries=256, slice_rows=64),
-                                   dict(tile_rows=37, slice_entries=1024, slice_rows=200)])
+@pytest.mark.parametrize("shape", [dict(tile_rows=128, slice_entries=256, slice_rows=64, slice_sort=0),
+                                   dict(tile_rows=37, slice_entries=1024, slice_rows=200, slice_sort=0),
+                                   dict(tile_rows=200, sort_rows=37),
+                                   dict(tile_rows=256, sort_rows=1)])
 def test_tile_shapes_trajectory_parity(shape):
     """Other SpMV tile shapes (the tuner's search space) change only the
     rounding order inside rows: iterates still agree with the oracle."""
@@ -588,7 +638,7 @@ def test_autotune_picks_a_measured_shape():
     lp = lpgen.scaled_powerlaw(21, 500, 1800)
     print("case autotune", flush=True)
     best, table, secs = autotune.autotune(lp, iters=256, slice_min_bytes=0)
-    assert len(table) == 2 + len(autotune.SLICE_SHAPES) - 1
+    assert len(table) == 2 + len(autotune.SORT_ROWS) + len(autotune.SLICE_SHAPES)
     assert best in [shape for shape, _ in table]
     assert all(ms > 0 for _, ms in table)
     r, x, y, _ = _gpu(lp, 1e-4, 100_000, slice_min_bytes=0, **best)
