@@ -25,26 +25,31 @@ HBM_PEAK_GBS = 8000.0
 METHODS = {"rhpdhg": 0, "r2hpdhg": 1, "rapdhg": 2}
 
 
-def algorithmic_bytes(n, m, nnz, s):
+def algorithmic_bytes(n, m, nnz, s, sorted_blocks=False):
     """Algorithmic bytes of one plain (non-check) step's two kernels.
     dual step : K entries (s + 4 B each), row pointers, one read of the
                 gathered 2x+ - x, and the row epilogue (read y, q, y0, write y);
     primal step: K^T entries, row pointers, one read of the gathered y, and
-                the column epilogue (read x, c, l, u, x0; write xbar, x)."""
-    dual = nnz * (s + 4) + 4 * (m + 1) + s * n + 4 * s * m
-    primal = nnz * (s + 4) + 4 * (n + 1) + s * m + 7 * s * n
+                the column epilogue (read x, c, l, u, x0; write xbar, x).
+    Column-sorted blocks read no row pointers (the row is packed into the
+    column index)."""
+    rp = 0 if sorted_blocks else 1
+    dual = nnz * (s + 4) + rp * 4 * (m + 1) + s * n + 4 * s * m
+    primal = nnz * (s + 4) + rp * 4 * (n + 1) + s * m + 7 * s * n
     return primal, dual
 
 
-def kernel_bytes(n, m, nnz, s, primal_sliced, dual_sliced, dual_sorted=False):
+def kernel_bytes(n, m, nnz, s, primal_sliced, dual_sliced, dual_sorted=False, plain_sorted=False):
     """Algorithmic bytes per launch of each of the four kernels of a plain
     step.  Where a product is column-sliced, its slice kernel is charged the
     matrix, row pointers and gathered vector, and the step kernel only its
     epilogue; the slice partial sums exchanged between the two are not
     algorithmic traffic and are charged to neither.  Column-sorted slices of
-    K carry no row pointers (the row is packed into the column index)."""
-    pmat = nnz * (s + 4) + 4 * (n + 1) + s * m
-    dmat = nnz * (s + 4) + s * n + (0 if dual_sliced and dual_sorted else 4 * (m + 1))
+    K, and column-sorted blocks of an unsliced product, carry no row
+    pointers (the row is packed into the column index)."""
+    pmat = nnz * (s + 4) + s * m + (0 if plain_sorted and not primal_sliced else 4 * (n + 1))
+    dsorted = dual_sorted if dual_sliced else plain_sorted
+    dmat = nnz * (s + 4) + s * n + (0 if dsorted else 4 * (m + 1))
     pepi, depi = 7 * s * n, 4 * s * m
     return {"primal_slice": pmat if primal_sliced else 0,
             "primal_step": pepi + (0 if primal_sliced else pmat),
@@ -52,7 +57,7 @@ def kernel_bytes(n, m, nnz, s, primal_sliced, dual_sliced, dual_sorted=False):
             "dual_step": depi + (0 if dual_sliced else dmat)}
 
 
-def batch_roofline(ksum, s):
+def batch_roofline(ksum, s, sorted_blocks=False):
     """Roofline of the dominant step kernel of a batch from the library's
     timings: per-kernel average durations (event-pair cost taken out) and the
     average sizes of the LPs the timed steps processed (finished LPs leave the
@@ -62,7 +67,7 @@ def batch_roofline(ksum, s):
     ev = ksum.get("event_pair_ms", 0.0) / kn
     avg = {k: max(ksum.get(k + "_ms", 0.0) / kn - ev, 0.0) for k in ("primal", "dual")}
     nnz, n, m = (ksum.get(k, 0.0) / kn for k in ("nnz", "n", "m"))
-    pb, db = algorithmic_bytes(n, m, nnz, s)
+    pb, db = algorithmic_bytes(n, m, nnz, s, sorted_blocks)
     byts = {"primal": pb, "dual": db}
     dom = max(avg, key=lambda k: avg[k])
     ach = byts[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
@@ -157,10 +162,15 @@ def cpu_pool_baseline(lps, results, method, sample=16):
                        f"mean {mean:.1f}s per LP")}
 
 
+def _det(args):
+    """--fixed-order: no column-sorted blocks (bit-reproducible sums)."""
+    return {"plain_sort": 0, "slice_sort": 0} if args.fixed_order else {}
+
+
 def _opts(halp, args, **kw):
     return halp.lp_default_options(
         method=METHODS[args.method],
-        precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64, **kw)
+        precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64, **_det(args), **kw)
 
 
 def _pct(v, q):
@@ -232,7 +242,7 @@ def run_batch(args):
     wall = time.perf_counter() - t0
     solved = sum(r["status"] in (1, 2, 3) for r in res) * args.steps
     s = 8 if args.precision == "fp64" else 4
-    roofline = batch_roofline(ksum, s)
+    roofline = batch_roofline(ksum, s, not args.fixed_order)
     st = [r["status"] for r in res]
     out = {"metric": "solved LPs/s + p99 latency at 1e-4 rel. KKT; SpMV HBM GB/s vs peak",
            "value": round(solved / wall, 3), "unit": "LPs/s", "n_gpus": 1, "steps": args.steps,
@@ -354,6 +364,9 @@ def main():
                     help="first run a plain streaming kernel (y = -x, FP64) over this many MB "
                          "(calibration of the HBM byte counters)")
     ap.add_argument("--no-graph", action="store_true", help="launch steps without hipGraphs")
+    ap.add_argument("--fixed-order", action="store_true",
+                    help="plain tiles and row-major slices with fixed-order sums instead of column-sorted "
+                         "blocks with LDS-atomic row sums")
     ap.add_argument("--autotune", action="store_true",
                     help="single-LP workloads: pick the SpMV tile shapes by timing them first "
                          "(outside the timed region; reported in config)")
@@ -411,7 +424,7 @@ def main():
         precision=halp.LP_PREC_FP32 if args.precision == "fp32" else halp.LP_PREC_FP64,
         profile=args.profile_every, verbose=args.verbose, use_graph=0 if args.no_graph else 1,
         **({} if args.cache_budget_mb is None else {"cache_budget_bytes": int(args.cache_budget_mb * 2**20)}),
-        **tuned)
+        **{**_det(args), **tuned})
 
     def step():
         h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,
@@ -456,7 +469,8 @@ def main():
     avg = {k: max(ksum[k + "_ms"] / kn - ev, 0.0) if ksum[k + "_ms"] > 0 else 0.0
            for k in ("primal_slice", "primal", "dual_slice", "dual")}
     primal_sliced, dual_sliced = avg["primal_slice"] > 0, avg["dual_slice"] > 0
-    kb = kernel_bytes(lp.n, lp.m, lp.nnz, s, primal_sliced, dual_sliced, opt.slice_sort == 1)
+    kb = kernel_bytes(lp.n, lp.m, lp.nnz, s, primal_sliced, dual_sliced, opt.slice_sort == 1,
+                      opt.plain_sort == 1)
     names = {"primal_slice": "primal_slice_step", "primal": "primal_step",
              "dual_slice": "dual_sorted_slice_step" if opt.slice_sort == 1 else "dual_slice_step",
              "dual": "dual_step"}

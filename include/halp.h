@@ -141,7 +141,13 @@ typedef struct {
                                bits of the iterates, may differ from run to run); 0: rows in
                                order with fixed-order sums (slice_entries, slice_rows) */
   int sort_rows;            /* rows per column-sorted slice tile, 1..4096 (default 4096;
-                               fewer when the slice is wider than 2^(32 - log2 rows)) */
+                               fewer when the slice is wider than 2^(32 - log2 rows));
+                               column-sorted plain blocks take at most 2048 of them */
+  int plain_sort;           /* products that are not column-sliced (K^T of the large LP,
+                               both products of small LPs): 1 (default) stores the rows of
+                               at most 1024 entries in column-sorted blocks of sort_rows
+                               (<= 2048) rows with LDS-atomic row sums (same caveat as
+                               slice_sort); 0: plain tiles (tile_rows) with fixed-order sums */
 } lp_options;
 
 typedef struct {

@@ -7,13 +7,14 @@ once per candidate shape, runs a fixed number of steps with every chunk
 timed by HIP events (their own cost taken out), and returns the shape with
 the least kernel time per step.
 
-Search (coordinate descent, 2 + 8 candidates):
-  1. tile_rows in {128, 256}: rows per plain workgroup tile (Kᵀ of the large
-     LP, every product of small LPs), with the default slices;
-  2. only if the LP has a column-sliced product, with the best tile_rows:
-     column-sorted slices of K with sort_rows in {1024, 2048} (4096, the
-     default, was timed in step 1), and fixed-order slices (slice_sort 0)
-     with slice_entries in {256, 512, 1024} x slice_rows in {64, 128}.
+Search (coordinate descent, 4 + 6 candidates):
+  1. the unsliced products (Kᵀ of the large LP, every product of small LPs):
+     column-sorted blocks with the default sort_rows (2048 rows per plain
+     block, 4096 per slice group) or sort_rows 1024, or fixed-order plain
+     tiles (plain_sort 0) of tile_rows in {128, 256};
+  2. only if the LP has a column-sliced product, with the best of step 1:
+     fixed-order slices (slice_sort 0) with slice_entries in {256, 512,
+     1024} x slice_rows in {64, 128}.
 
 Each candidate's solve starts from scratch and its iterates are discarded;
 the chosen options are then passed to the real solve.
@@ -26,8 +27,7 @@ from . import (lp_create, lp_default_options, lp_destroy, lp_kernel_times, lp_so
                make_problems, lp_batch_create_from, lp_batch_solve, lp_batch_kernel_times,
                lp_batch_destroy)
 
-TILE_ROWS = (128, 256)
-SORT_ROWS = (1024, 2048)
+FIRST = ({}, {"sort_rows": 1024}, {"plain_sort": 0, "tile_rows": 128}, {"plain_sort": 0, "tile_rows": 256})
 SLICE_SHAPES = tuple((e, r) for e in (256, 512, 1024) for r in (64, 128))
 
 
@@ -85,14 +85,13 @@ def autotune(lp_or_lps, iters: int = 640, stream=None, **base):
         return ms, sliced
 
     best, best_ms, sliced = None, float("inf"), False
-    for r in TILE_ROWS:
-        ms, sl = measure({"tile_rows": r})
+    for shape in FIRST:
+        ms, sl = measure(shape)
         sliced |= sl
         if ms < best_ms:
-            best, best_ms = {"tile_rows": r}, ms
+            best, best_ms = dict(shape), ms
     if sliced:
-        cands = [{**best, "slice_sort": 1, "sort_rows": r} for r in SORT_ROWS]
-        cands += [{**best, "slice_sort": 0, "slice_entries": e, "slice_rows": r} for e, r in SLICE_SHAPES]
+        cands = [{**best, "slice_sort": 0, "slice_entries": e, "slice_rows": r} for e, r in SLICE_SHAPES]
         for shape in cands:
             ms, _ = measure(shape)
             if ms < best_ms:

@@ -72,6 +72,7 @@ halp::Options to_opts(const lp_options* o) {
   r.slice_rows = o->slice_rows;
   r.slice_sort = o->slice_sort;
   r.sort_rows = o->sort_rows;
+  r.plain_sort = o->plain_sort;
   return r;
 }
 
@@ -82,6 +83,7 @@ void check_opts(const halp::Options& o) {
   if (o.slice_entries != 256 && o.slice_entries != 512 && o.slice_entries != 1024)
     throw halp::Error(LP_ERR_INVALID, "slice_entries must be 256, 512 or 1024");
   if (o.slice_sort < 0 || o.slice_sort > 1) throw halp::Error(LP_ERR_INVALID, "slice_sort must be 0 or 1");
+  if (o.plain_sort < 0 || o.plain_sort > 1) throw halp::Error(LP_ERR_INVALID, "plain_sort must be 0 or 1");
   if (o.sort_rows < 1 || o.sort_rows > halp::kSortRows)
     throw halp::Error(LP_ERR_INVALID, "sort_rows must be in 1..4096");
   if (o.restart_mode == 1 && o.fixed_restart_len < 1)
@@ -395,6 +397,7 @@ void lp_default_options(lp_options* o) {
   o->slice_rows = d.slice_rows;
   o->slice_sort = d.slice_sort;
   o->sort_rows = d.sort_rows;
+  o->plain_sort = d.plain_sort;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }
@@ -647,7 +650,7 @@ halp::Problem request_problem(const Request& r) {
 // spaces for a reference mix of n = 4 m and nnz = 36 m (the batched sizes)
 bool server_caps(int64_t budget, int precision, int64_t* cap_m, int64_t* cap_n, int64_t* cap_nz) {
   const int64_t sz = precision == 1 ? 4 : 8;
-  const int64_t per_row = 4 + 24 + 10 * sz, per_col = 4 + 40 + 11 * sz;
+  const int64_t per_row = 4 + 24 + 12 * sz, per_col = 4 + 40 + 13 * sz;
   const int64_t per_nz = 24 + (precision == 1 ? 8 : 0);
   const int64_t unit = per_row + 4 * per_col + 36 * per_nz;
   const int64_t u = budget / unit;

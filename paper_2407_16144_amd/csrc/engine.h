@@ -61,6 +61,7 @@ struct Options {
   int slice_entries = kSliceNB;    // entries per slice tile: 256, 512 or 1024
   int slice_rows = kSliceRows;     // rows per sliced row group (<= 256)
   int slice_sort = 1;              // sliced K: column-sorted tiles, LDS-atomic row sums
+  int plain_sort = 1;              // unsliced K / K^T: column-sorted blocks, LDS-atomic row sums
   int sort_rows = kSortRows;       // rows per column-sorted tile (<= kSortRows)
   int restart_mode = 0;            // 0 adaptive, 1 fixed frequency, 2 none
   int64_t fixed_restart_len = 0;   // k* of the fixed-frequency rule

@@ -249,7 +249,7 @@ class Engine final : public EngineBase {
 
   int64_t footprint(int64_t n, int64_t m, int64_t nnz) const override {
     const int64_t s = sizeof(T);
-    const int64_t per_row = 4 + 3 * 8 + 10 * s, per_col = 4 + 5 * 8 + 11 * s;
+    const int64_t per_row = 4 + 3 * 8 + 12 * s, per_col = 4 + 5 * 8 + 13 * s;
     const int64_t per_nz = 8 + 16 + (sizeof(T) == 8 ? 0 : 2 * s);
     return per_row * (m + 1) + per_col * (n + 1) + per_nz * nnz;
   }
@@ -293,6 +293,7 @@ class Engine final : public EngineBase {
                   const std::vector<int4>& nr);
   void slice_matrix(int id, bool dual);
   void slice_sorted(int id);
+  void sort_blocks(int id, bool dual);
   IterArgs<T> args() const;
   void pull_states();
 
@@ -321,6 +322,7 @@ class Engine final : public EngineBase {
   // column-sliced layout
   int32_t *brpK = nullptr, *brpKT = nullptr;
   T *spartD = nullptr, *spartP = nullptr;
+  T *kt1_ = nullptr, *kt2_ = nullptr, *kx1_ = nullptr, *kx2_ = nullptr;  // sorted blocks' eval products
   uint8_t *actx = nullptr, *acty = nullptr;  // activity at the last check (two-stage diagnostics)
   Blk *d_schedPS = nullptr, *d_schedDS = nullptr;
   int64_t capPS_ = 0, capDS_ = 0, nPS_ = 0, nDS_ = 0;
@@ -370,6 +372,12 @@ void Engine<T>::allocate() {
   for (T** p : {&c, &l, &u, &x, &x0, &xbar, &xT, &ktyp, &cx1, &cx2, &xs}) dalloc(p, NS_);
   dalloc(&actx, NS_);
   dalloc(&acty, MS_);
+  if (opt_.plain_sort) {
+    dalloc(&kx1_, MS_);
+    dalloc(&kx2_, MS_);
+    dalloc(&kt1_, NS_);
+    dalloc(&kt2_, NS_);
+  }
   dalloc(&brpK, 2 * kSlices * MS_);
   dalloc(&brpKT, 2 * kSlices * NS_);
   dalloc(&d_st, nslots_);
@@ -420,6 +428,10 @@ void Engine<T>::release_all() {
   dfree(brpK);
   dfree(brpKT);
   dfree(spartD);
+  dfree(kt1_);
+  dfree(kt2_);
+  dfree(kx1_);
+  dfree(kx2_);
   dfree(spartP);
   dfree(d_schedPS);
   dfree(d_schedDS);
@@ -452,6 +464,10 @@ IterArgs<T> Engine<T>::args() const {
   A.brpKT = brpKT;
   A.spartD = spartD;
   A.spartP = spartP;
+  A.kt1 = kt1_;
+  A.kt2 = kt2_;
+  A.kx1 = kx1_;
+  A.kx2 = kx2_;
   A.MS = MS_;
   A.NS = NS_;
   A.c = c;
@@ -810,6 +826,9 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
       slice_matrix(id, true);
     if (opt_.slice_min_bytes >= 0 && S.nnz > 0 && S.m * (int64_t)sizeof(T) > opt_.slice_min_bytes)
       slice_matrix(id, false);
+    // the other products: column-sorted blocks
+    if (opt_.plain_sort && S.bDS.empty()) sort_blocks(id, true);
+    if (opt_.plain_sort && S.bPS.empty()) sort_blocks(id, false);
   }
   sched_dirty_ = true;
   for (int id : ids) slots_[id].watched = true;
@@ -1062,6 +1081,123 @@ void Engine<T>::slice_matrix(int id, bool dual) {
   // slice partial sums live in space-sized buffers, allocated on first use
   if (dual && !spartD) dalloc(&spartD, 3 * kSlices * MS_);
   if (!dual && !spartP) dalloc(&spartP, 3 * kSlices * NS_);
+}
+
+// Column-sorted blocks of one LP's K (dual = true) or K^T, for a product
+// that is not column-sliced: rows longer than a plain tile keep a long
+// block; the other rows go to blocks of at most min(sort_rows,
+// kSortRowsPlain) rows and kSortEntries entries whose entries are put in
+// column order (keys sorted within each block on the device), each column
+// index packed with the entry's row in the block (see blk_rowbits).
+template <class T>
+void Engine<T>::sort_blocks(int id, bool dual) {
+  Slot& S = slots_[id];
+  const int64_t nrows = dual ? S.m : S.n;
+  const int64_t base = dual ? S.row0 : S.col0;
+  const int64_t c0 = dual ? S.col0 : S.row0;
+  const int64_t width = dual ? S.n : S.m;
+  const int32_t* rpd = dual ? K_rp : KT_rp;
+  int32_t* ci = dual ? K_ci : KT_ci;
+  T* val = dual ? K_v : KT_v;
+  double* v64 = dual ? K_v64 : KT_v64;
+  if (nrows == 0 || S.nnz == 0) return;
+  int cb = 0;
+  while (((int64_t)1 << cb) < width) ++cb;
+  if (cb >= 32) return;
+  int64_t rows = std::min<int64_t>(std::min<int64_t>(opt_.sort_rows, kSortRowsPlain), (int64_t)1 << (32 - cb));
+  int rb = 0;
+  while (((int64_t)1 << rb) < rows) ++rb;
+  std::vector<int32_t> rp(nrows + 1);
+  HIPCHECK(hipMemcpy(rp.data(), rpd + base, sizeof(int32_t) * (nrows + 1), hipMemcpyDeviceToHost));
+  std::vector<Blk> out, sorted;
+  std::vector<int32_t> b_off, e_off;
+  auto emit = [&](int64_t a, int64_t e, int kind) {
+    Blk k;
+    k.r0 = (int32_t)(base + a);
+    k.r1 = (int32_t)(base + e);
+    k.inst = id;
+    k.meta = blk_meta(kind, 1, 0) | (kind == BK_SORTED ? (rb << 25) : 0);
+    k.gid = (int32_t)out.size();
+    k.rp_off = kind == BK_SORTED ? (int32_t)c0 : 0;
+    k.p0 = rp[a];
+    k.pn = rp[e] - rp[a];
+    out.push_back(k);
+    if (kind == BK_SORTED) {
+      sorted.push_back(k);
+      b_off.push_back((int32_t)(k.p0 - S.nz0));
+      e_off.push_back((int32_t)(k.p0 + k.pn - S.nz0));
+    }
+  };
+  int64_t start = 0, acc = 0;
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t len = (int64_t)rp[r + 1] - rp[r];
+    if (len > kPlainNB) {
+      if (r > start) emit(start, r, BK_SORTED);
+      emit(r, r + 1, BK_LONG);
+      start = r + 1;
+      acc = 0;
+      continue;
+    }
+    if ((r - start) >= rows || acc + len > kSortEntries) {
+      if (r > start) emit(start, r, BK_SORTED);
+      start = r;
+      acc = 0;
+    }
+    acc += len;
+  }
+  if (nrows > start) emit(start, nrows, BK_SORTED);
+  if (!sorted.empty()) {
+    const int64_t nnz = S.nnz;
+    const int nseg = (int)sorted.size();
+    Blk* d_blk = nullptr;
+    int32_t *d_b = nullptr, *d_e = nullptr, *src_in = nullptr, *src_out = nullptr;
+    uint32_t *key_in = nullptr, *key_out = nullptr;
+    T* v_tmp = nullptr;
+    double* v64_tmp = nullptr;
+    dalloc(&d_blk, nseg);
+    dalloc(&d_b, nseg);
+    dalloc(&d_e, nseg);
+    dalloc(&key_in, nnz);
+    dalloc(&key_out, nnz);
+    dalloc(&src_in, nnz);
+    dalloc(&src_out, nnz);
+    dalloc(&v_tmp, nnz);
+    if (sizeof(T) != 8) dalloc(&v64_tmp, nnz);
+    HIPCHECK(hipMemcpyAsync(d_blk, sorted.data(), sizeof(Blk) * nseg, hipMemcpyHostToDevice, stream_));
+    HIPCHECK(hipMemcpyAsync(d_b, b_off.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, stream_));
+    HIPCHECK(hipMemcpyAsync(d_e, e_off.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, stream_));
+    HIPCHECK(hipMemcpyAsync(v_tmp, val + S.nz0, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
+    if (v64_tmp)
+      HIPCHECK(hipMemcpyAsync(v64_tmp, v64 + S.nz0, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
+    sorted_keys_kernel<<<(unsigned)nseg, kThreads, 0, stream_>>>(d_blk, rpd, ci, S.nz0, key_in, src_in);
+    HIPCHECK(hipGetLastError());
+    size_t tmp_bytes = 0;
+    HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tmp_bytes, key_in, key_out, src_in, src_out,
+                                                         (int)nnz, nseg, d_b, d_e, 0, 32, stream_));
+    void* tmp = nullptr;
+    HIPCHECK(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
+    HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, src_in, src_out,
+                                                         (int)nnz, nseg, d_b, d_e, 0, 32, stream_));
+    sorted_block_gather_kernel<T><<<(unsigned)nseg, kThreads, 0, stream_>>>(d_blk, S.nz0, key_out, src_out, val,
+                                                                           v64, ci, v_tmp, v64_tmp);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(val + S.nz0, v_tmp, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
+    if (v64_tmp)
+      HIPCHECK(hipMemcpyAsync(v64 + S.nz0, v64_tmp, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
+    HIPCHECK(hipStreamSynchronize(stream_));
+    (void)hipFree(tmp);
+    dfree(d_blk);
+    dfree(d_b);
+    dfree(d_e);
+    dfree(key_in);
+    dfree(key_out);
+    dfree(src_in);
+    dfree(src_out);
+    dfree(v_tmp);
+    dfree(v64_tmp);
+  }
+  if (dual) S.bD = out;
+  else S.bP = out;
 }
 
 // Column-sorted slicing of one LP's K (the dual product's gathers): row

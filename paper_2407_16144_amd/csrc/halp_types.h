@@ -27,7 +27,7 @@ template <class T> struct Tile { static constexpr int NB = kPlainNB; };
 
 enum Mode : int { M_SKIP = 0, M_NORMAL = 1, M_CHECK = 2, M_EVAL = 3, M_RESID = 4 };
 enum Phase : int { PH_NORMAL = 0, PH_EVAL = 1, PH_RESID = 2 };
-enum BlkKind : int { BK_STREAM = 0, BK_LONG = 1, BK_PAD = 2 };
+enum BlkKind : int { BK_STREAM = 0, BK_LONG = 1, BK_PAD = 2, BK_SORTED = 3 };
 
 // Column slices of a sliced matrix: one per XCD, so that consecutive
 // workgroups (dispatched round-robin over the XCDs) gather from a slice of the
@@ -64,6 +64,11 @@ __host__ __device__ inline bool blk_nt(const Blk& b) { return (b.meta & kBlkNT) 
 // (its row sums sit in LDS) and at most kSortEntries entries per slice.
 constexpr int kSortRows = 4096;
 constexpr int kSortEntries = 1 << 16;
+// A plain block of the step kernels may be column-sorted too (kind
+// BK_SORTED, same packing, rp_off = the LP's first column): at most
+// kSortRowsPlain rows (its row sums share the step kernel's LDS with the
+// plain tile), rows of at most kPlainNB entries.
+constexpr int kSortRowsPlain = 2048;
 __host__ __device__ inline int blk_rowbits(const Blk& b) { return (b.meta >> 25) & 31; }
 __host__ __device__ inline int32_t blk_meta(int kind, int nsl, int slice) {
   return kind | (nsl << 8) | (slice << 16);

@@ -47,6 +47,12 @@ struct IterArgs {
   // slice partial row sums of sliced row groups: [3][kSlices][space]
   T* spartD;   // m-space (dual step)
   T* spartP;   // n-space (primal step)
+  // eval-step products of column-sorted blocks with the ray candidates:
+  // K^T cy1, K^T cy2 (n-space) and K cx1, K cx2 (m-space)
+  T* kt1;
+  T* kt2;
+  T* kx1;
+  T* kx2;
   int64_t MS, NS;
   // control
   InstState* st;

@@ -303,16 +303,216 @@ __device__ __forceinline__ T rec_proj(T d, bool lf, bool uf) {
 // primal step (rows of K^T = variables)
 // ---------------------------------------------------------------------------
 
+// Row sums of one column-sorted block (a sorted slice block, or a plain
+// BK_SORTED block) for the gathered vector src:
+// consecutive entries gather nearby elements of the slice, so the rows of
+// the group share the cache lines of their gathers.  Products go to the LDS
+// row sums s_row by atomic adds, so the order of the additions within a row
+// is not fixed (the last bits of a sum can differ from run to run).
+template <class T, bool NT>
+__device__ __forceinline__ void sorted_rows_sum(const Blk& b, const uint32_t* __restrict__ w,
+                                                const T* __restrict__ val, const T* __restrict__ src,
+                                                T* s_row) {
+  constexpr int U = 8;  // entries in flight per thread
+  const int rb = blk_rowbits(b);
+  const uint32_t rmask = (1u << rb) - 1u;
+  const T* srcb = src + b.rp_off;
+  for (int e0 = threadIdx.x; e0 < b.pn; e0 += kThreads * U) {
+    uint32_t k[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < b.pn) {
+        k[u] = ld_entry<NT>(w + b.p0 + e);
+        v[u] = ld_entry<NT>(val + b.p0 + e);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < b.pn) atomicAdd(&s_row[k[u] & rmask], v[u] * srcb[k[u] >> rb]);
+    }
+  }
+}
+
+// One variable's part of a primal step (rows of K^T): j is its space
+// position, kty its row sum (K^T y, or K^T yT at an eval step, where g1 and
+// g2 are K^T cy1 and K^T cy2; at a residual step the caller passes T(z) as
+// xo and x0j and K^T yT as kty).  Adds the check / eval / residual terms of
+// the variable to ps.
+template <class T>
+__device__ __forceinline__ void primal_row(const IterArgs<T>& A, const InstState& S, int mode, int64_t g,
+                                           int64_t j, T cj, T lj, T uj, T xo, T x0j, T kty, T g1, T g2,
+                                           double (&ps)[kNS]) {
+  const bool resid = (mode == M_RESID);
+  const bool lf = isfinite(lj), uf = isfinite(uj);
+  if (mode == M_EVAL) {
+    const T g0 = kty;
+    A.ktyp[j] = g0;
+    const double dc = A.Dc[j];
+    const double r = (double)cj - (double)g0;
+    const double lam = (lf && uf) ? r : lf ? fmax(r, 0.0) : uf ? fmin(r, 0.0) : 0.0;
+    const double rd = (r - lam) / dc;
+    ps[0] += rd * rd;
+    ps[1] += (lf ? (double)lj * fmax(lam, 0.0) : 0.0) - (uf ? (double)uj * fmax(-lam, 0.0) : 0.0);
+#pragma unroll
+    for (int a = 1; a <= 2; ++a) {
+      const double gg = (double)(a == 1 ? g1 : g2);
+      double sv = 0.0, vv = 0.0;
+      if (gg > 0.0) {
+        if (uf) sv = (double)uj * gg; else vv = gg / dc;
+      } else if (gg < 0.0) {
+        if (lf) sv = (double)lj * gg; else vv = -gg / dc;
+      }
+      ps[2 * a] += sv;
+      ps[2 * a + 1] += vv * vv;
+    }
+    return;
+  }
+  const T tau = (T)S.tau;
+  const T xp = clampT<T>(xo - tau * (cj - kty), lj, uj);
+  const T xb = (T)2 * xp - xo;
+  const int64_t k = g - S.kbase;
+  T xn, xc = xp;  // next iterate; check candidate (T(z), or the epoch average)
+  if (S.avg) {
+    // plain PDHG step; running sum of z^{n,0..k+1} (restarted at k = 0)
+    const T xsum = (k == 0 ? xo : A.xs[j]) + xp;
+    A.xs[j] = xsum;
+    xn = xp;
+    if (mode == M_CHECK) xc = xsum / (T)(k + 2);
+  } else {
+    const double w = (double)(k + 1) / (double)(k + 2);
+    const T xh = S.reflect ? xb : xp;
+    xn = (T)w * xh + (T)(1.0 - w) * x0j;
+  }
+  A.xbar[j] = xb;
+  A.x[j] = xn;
+  if (resid) {
+    A.x0[j] = xo;
+    const double d = (double)xo - (double)xp;
+    ps[0] += d * d;
+  } else if (mode == M_CHECK) {
+    A.xT[j] = xc;
+    const double d = (double)xo - (double)xp;
+    const double ad = (double)xc - (double)x0j;
+    const T d1 = rec_proj<T>(xp - xo, lf, uf);
+    const T d2 = rec_proj<T>(xo - x0j, lf, uf);
+    A.cx1[j] = d1;
+    A.cx2[j] = d2;
+    ps[0] += d * d;
+    ps[1] += ad * ad;
+    ps[2] += (double)cj * (double)xc;
+    ps[3] += (double)cj * (double)d1;
+    ps[4] += (double)cj * (double)d2;
+    const uint8_t act = (lf && xp == lj) ? 1 : (uf && xp == uj) ? 2 : 0;
+    const uint8_t was = A.actx[j];
+    A.actx[j] = act;
+    ps[5] += (was != 255 && was != act) ? 1.0 : 0.0;
+  }
+}
+
+// Row sums of a column-sorted block (BK_SORTED) for the gathered vector src,
+// left in s_row[0 .. nrows).
+template <class T>
+__device__ __forceinline__ void sorted_pass(const Blk& b, const int32_t* __restrict__ ci,
+                                            const T* __restrict__ val, const T* __restrict__ src, T* s_row) {
+  const int nrows = b.r1 - b.r0;
+  for (int r = threadIdx.x; r < nrows; r += kThreads) s_row[r] = (T)0;
+  lds_barrier();
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(ci);
+  if (blk_nt(b)) sorted_rows_sum<T, true>(b, w, val, src, s_row);
+  else sorted_rows_sum<T, false>(b, w, val, src, s_row);
+  lds_barrier();
+}
+
+// The same, stored to out[b.r0 + r] by the thread that later reads it back
+// (row r is handled by thread r mod kThreads in every loop over a block).
+template <class T>
+__device__ __forceinline__ void sorted_pass_to(const Blk& b, const int32_t* __restrict__ ci,
+                                               const T* __restrict__ val, const T* __restrict__ src, T* s_row,
+                                               T* out) {
+  sorted_pass<T>(b, ci, val, src, s_row);
+  const int nrows = b.r1 - b.r0;
+  for (int r = threadIdx.x; r < nrows; r += kThreads) out[(int64_t)b.r0 + r] = s_row[r];
+  lds_barrier();
+}
+
+// A primal step over a column-sorted block of K^T rows (up to kSortRowsPlain
+// variables): the products with y (yT, cy1, cy2 at an eval step) are added
+// into LDS row sums, then each thread takes the epilogue of every
+// kThreads-th variable.
+template <class T>
+__device__ void primal_sorted(const IterArgs<T>& A, const Blk& b, int step, T* s_row,
+                              double (*s_red)[kNS], double* s_out) {
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP) return;
+  const bool resid = (mode == M_RESID);
+  const int nrows = b.r1 - b.r0;
+  if (mode == M_EVAL) {
+    sorted_pass_to<T>(b, A.KT_ci, A.KT_v, A.cy1, s_row, A.kt1);
+    sorted_pass_to<T>(b, A.KT_ci, A.KT_v, A.cy2, s_row, A.kt2);
+    sorted_pass<T>(b, A.KT_ci, A.KT_v, A.yT, s_row);
+  } else if (!resid) {
+    sorted_pass<T>(b, A.KT_ci, A.KT_v, A.y, s_row);
+  }
+  double ps[kNS];
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += kThreads) {
+    const int64_t j = (int64_t)b.r0 + r;
+    const T cj = A.c[j], lj = A.l[j], uj = A.u[j];
+    T xo, x0j, kty, g1 = 0, g2 = 0;
+    if (resid) {
+      xo = A.xT[j];
+      x0j = xo;
+      kty = A.ktyp[j];
+    } else {
+      xo = A.x[j];
+      x0j = A.x0[j];
+      kty = s_row[r];
+      if (mode == M_EVAL) {
+        g1 = A.kt1[j];
+        g2 = A.kt2[j];
+      }
+    }
+    primal_row<T>(A, S, mode, g, j, cj, lj, uj, xo, x0j, kty, g1, g2, ps);
+  }
+  if (mode != M_NORMAL) {
+    block_sum_ns(ps, s_red, s_out);
+    if (threadIdx.x < kNS) A.partP[(int64_t)b.gid * kNS + threadIdx.x] = s_out[threadIdx.x];
+  }
+}
+
+// LDS of a step kernel: the plain tile's products, row sums and row
+// pointers, or the row sums of a column-sorted block (never both).
+template <class T>
+union StepSmem {
+  struct {
+    T prod[Tile<T>::NB];
+    T rsum[3][kMaxRows];
+    int rp[kMaxRows + 1];
+  } p;
+  T rows[kSortRowsPlain];
+};
+
 template <class T>
 __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step) {
-  __shared__ T s_prod[Tile<T>::NB];
-  __shared__ T s_rsum[3][kMaxRows];
-  __shared__ int s_rp[kMaxRows + 1];
+  __shared__ StepSmem<T> sm;
   __shared__ double s_red[kThreads / 64][kNS];
   __shared__ double s_out[kNS];
+  T* s_prod = sm.p.prod;
+  T (*s_rsum)[kMaxRows] = sm.p.rsum;
+  int* s_rp = sm.p.rp;
 
   const Blk b = A.schedP[blockIdx.x];
   if (blk_kind(b) == BK_PAD) return;
+  if (blk_kind(b) == BK_SORTED) {
+    primal_sorted<T>(A, b, step, sm.rows, s_red, s_out);
+    return;
+  }
   const int nrows = b.r1 - b.r0;
   const int t = threadIdx.x;
   const bool own = t < nrows;
@@ -353,71 +553,9 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
 #pragma unroll
   for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
   if (own) {
-    const bool lf = isfinite(lj), uf = isfinite(uj);
-    if (mode == M_EVAL) {
-      const T g0 = s_rsum[0][t];
-      A.ktyp[j] = g0;
-      const double dc = A.Dc[j];
-      const double r = (double)cj - (double)g0;
-      const double lam = (lf && uf) ? r : lf ? fmax(r, 0.0) : uf ? fmin(r, 0.0) : 0.0;
-      const double rd = (r - lam) / dc;
-      ps[0] = rd * rd;
-      ps[1] = (lf ? (double)lj * fmax(lam, 0.0) : 0.0) - (uf ? (double)uj * fmax(-lam, 0.0) : 0.0);
-#pragma unroll
-      for (int a = 1; a <= 2; ++a) {
-        const double gg = (double)s_rsum[a][t];
-        double sv = 0.0, vv = 0.0;
-        if (gg > 0.0) {
-          if (uf) sv = (double)uj * gg; else vv = gg / dc;
-        } else if (gg < 0.0) {
-          if (lf) sv = (double)lj * gg; else vv = -gg / dc;
-        }
-        ps[2 * a] = sv;
-        ps[2 * a + 1] = vv * vv;
-      }
-    } else {
-      if (!resid) kty = s_rsum[0][t];
-      const T tau = (T)S.tau;
-      const T xp = clampT<T>(xo - tau * (cj - kty), lj, uj);
-      const T xb = (T)2 * xp - xo;
-      const int64_t k = g - S.kbase;
-      T xn, xc = xp;  // next iterate; check candidate (T(z), or the epoch average)
-      if (S.avg) {
-        // plain PDHG step; running sum of z^{n,0..k+1} (restarted at k = 0)
-        const T xsum = (k == 0 ? xo : A.xs[j]) + xp;
-        A.xs[j] = xsum;
-        xn = xp;
-        if (mode == M_CHECK) xc = xsum / (T)(k + 2);
-      } else {
-        const double w = (double)(k + 1) / (double)(k + 2);
-        const T xh = S.reflect ? xb : xp;
-        xn = (T)w * xh + (T)(1.0 - w) * x0j;
-      }
-      A.xbar[j] = xb;
-      A.x[j] = xn;
-      if (resid) {
-        A.x0[j] = xo;
-        const double d = (double)xo - (double)xp;
-        ps[0] = d * d;
-      } else if (mode == M_CHECK) {
-        A.xT[j] = xc;
-        const double d = (double)xo - (double)xp;
-        const double ad = (double)xc - (double)x0j;
-        const T d1 = rec_proj<T>(xp - xo, lf, uf);
-        const T d2 = rec_proj<T>(xo - x0j, lf, uf);
-        A.cx1[j] = d1;
-        A.cx2[j] = d2;
-        ps[0] = d * d;
-        ps[1] = ad * ad;
-        ps[2] = (double)cj * (double)xc;
-        ps[3] = (double)cj * (double)d1;
-        ps[4] = (double)cj * (double)d2;
-        const uint8_t act = (lf && xp == lj) ? 1 : (uf && xp == uj) ? 2 : 0;
-        const uint8_t was = A.actx[j];
-        A.actx[j] = act;
-        ps[5] = (was != 255 && was != act) ? 1.0 : 0.0;
-      }
-    }
+    const bool eval = (mode == M_EVAL);
+    primal_row<T>(A, S, mode, g, j, cj, lj, uj, xo, x0j, resid ? kty : s_rsum[0][t],
+                  eval ? s_rsum[1][t] : (T)0, eval ? s_rsum[2][t] : (T)0, ps);
   }
   if (mode != M_NORMAL) {
     block_sum_ns(ps, s_red, s_out);
@@ -473,38 +611,6 @@ __global__ __launch_bounds__(kThreads) void primal_slice_step(IterArgs<T> A, int
 template <class T, int NB>
 __global__ __launch_bounds__(kThreads) void dual_slice_step(IterArgs<T> A, int step) {
   slice_body<T, true, NB>(A, step);
-}
-
-// Row sums of one column-sorted slice block for the gathered vector src:
-// consecutive entries gather nearby elements of the slice, so the rows of
-// the group share the cache lines of their gathers.  Products go to the LDS
-// row sums s_row by atomic adds, so the order of the additions within a row
-// is not fixed (the last bits of a sum can differ from run to run).
-template <class T, bool NT>
-__device__ __forceinline__ void sorted_rows_sum(const Blk& b, const uint32_t* __restrict__ w,
-                                                const T* __restrict__ val, const T* __restrict__ src,
-                                                T* s_row) {
-  constexpr int U = 8;  // entries in flight per thread
-  const int rb = blk_rowbits(b);
-  const uint32_t rmask = (1u << rb) - 1u;
-  const T* srcb = src + b.rp_off;
-  for (int e0 = threadIdx.x; e0 < b.pn; e0 += kThreads * U) {
-    uint32_t k[U];
-    T v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kThreads;
-      if (e < b.pn) {
-        k[u] = ld_entry<NT>(w + b.p0 + e);
-        v[u] = ld_entry<NT>(val + b.p0 + e);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kThreads;
-      if (e < b.pn) atomicAdd(&s_row[k[u] & rmask], v[u] * srcb[k[u] >> rb]);
-    }
-  }
 }
 
 // Partial row sums of one column slice of a sorted row group of K (written
@@ -658,16 +764,143 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
 // dual step (rows of K = constraints) + per-LP controller
 // ---------------------------------------------------------------------------
 
+// One constraint's part of a dual step (rows of K): i is its space
+// position, s0 its row sum (K xbar, or K xT at an eval step, where a1 and a2
+// are K cx1 and K cx2; at a residual step the caller passes T(z) as yo and
+// y0i and the saved K x+ as kxpi).  Adds the check / eval / residual terms
+// of the row to ps.
+template <class T>
+__device__ __forceinline__ void dual_row(const IterArgs<T>& A, const InstState& S, int mode, int64_t g,
+                                         int64_t i, T qi, T yo, T y0i, T kxpi, T s0, T a1, T a2,
+                                         double (&ps)[kNS]) {
+  const bool resid = (mode == M_RESID);
+  const bool ineq = (i - S.row0) >= S.m_eq;
+  if (mode == M_EVAL) {
+    A.kxp[i] = s0;
+    const double dr = A.Dr[i];
+    double r = ((double)s0 - (double)qi) / dr;
+    if (ineq) r = fmin(r, 0.0);
+    ps[0] += r * r;
+    ps[1] += (double)A.dy[i] * ((double)s0 - (double)A.kxbar[i]);
+#pragma unroll
+    for (int a = 1; a <= 2; ++a) {
+      const double av = (double)(a == 1 ? a1 : a2) / dr;
+      if (ineq) {
+        const double mv = fmin(av, 0.0);
+        ps[2 * a + 1] += mv * mv;
+      } else {
+        ps[2 * a] += av * av;
+      }
+    }
+    return;
+  }
+  const T sigma = (T)S.sigma;
+  T yp = yo + sigma * (qi - s0);
+  if (ineq) yp = fmax(yp, (T)0);
+  const T yb = (T)2 * yp - yo;
+  const int64_t k = g - S.kbase;
+  T yc = yp;  // check candidate
+  if (S.avg) {
+    const T ysum = (k == 0 ? yo : A.ys[i]) + yp;
+    A.ys[i] = ysum;
+    A.y[i] = yp;
+    if (mode == M_CHECK) yc = ysum / (T)(k + 2);
+  } else {
+    const double w = (double)(k + 1) / (double)(k + 2);
+    const T yh = S.reflect ? yb : yp;
+    A.y[i] = (T)w * yh + (T)(1.0 - w) * y0i;
+  }
+  if (resid) {
+    A.y0[i] = yo;
+    const double d = (double)yo - (double)yp;
+    ps[0] += d * d;
+    ps[1] += d * (0.5 * ((double)kxpi - (double)s0));
+  } else if (mode == M_CHECK) {
+    A.yT[i] = yc;
+    const T dyv = yo - yp;
+    A.dy[i] = dyv;
+    A.kxbar[i] = s0;
+    T e1 = yp - yo, e2 = yo - y0i;
+    if (ineq) {
+      e1 = fmax(e1, (T)0);
+      e2 = fmax(e2, (T)0);
+    }
+    A.cy1[i] = e1;
+    A.cy2[i] = e2;
+    const double ad = (double)yc - (double)y0i;
+    ps[0] += (double)dyv * (double)dyv;
+    ps[1] += ad * ad;
+    ps[2] += (double)qi * (double)yc;
+    ps[3] += (double)qi * (double)e1;
+    ps[4] += (double)qi * (double)e2;
+    const uint8_t act = (ineq && yp == (T)0) ? 1 : 0;
+    const uint8_t was = A.acty[i];
+    A.acty[i] = act;
+    ps[5] += (was != 255 && was != act) ? 1.0 : 0.0;
+  }
+}
+
+// A dual step over a column-sorted block of K rows (up to kSortRowsPlain
+// constraints): products with xbar (xT, cx1, cx2 at an eval step) added into
+// LDS row sums, then each thread takes the epilogue of every kThreads-th row.
+template <class T>
+__device__ void dual_sorted(const IterArgs<T>& A, const Blk& b, int step, T* s_row, double (*s_red)[kNS],
+                            double* s_out) {
+  const InstState& S = A.st[b.inst];
+  const int64_t g = *A.gbase + step;
+  const int mode = step_mode(S, g);
+  if (mode == M_SKIP) return;
+  const bool resid = (mode == M_RESID);
+  const int nrows = b.r1 - b.r0;
+  if (mode == M_EVAL) {
+    sorted_pass_to<T>(b, A.K_ci, A.K_v, A.cx1, s_row, A.kx1);
+    sorted_pass_to<T>(b, A.K_ci, A.K_v, A.cx2, s_row, A.kx2);
+    sorted_pass<T>(b, A.K_ci, A.K_v, A.xT, s_row);
+  } else {
+    sorted_pass<T>(b, A.K_ci, A.K_v, A.xbar, s_row);
+  }
+  double ps[kNS];
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += kThreads) {
+    const int64_t i = (int64_t)b.r0 + r;
+    const T qi = A.q[i];
+    T yo, y0i, kxpi = 0, a1 = 0, a2 = 0;
+    if (resid) {
+      yo = A.yT[i];
+      y0i = yo;
+      kxpi = A.kxp[i];
+    } else {
+      yo = A.y[i];
+      y0i = A.y0[i];
+    }
+    if (mode == M_EVAL) {
+      a1 = A.kx1[i];
+      a2 = A.kx2[i];
+    }
+    dual_row<T>(A, S, mode, g, i, qi, yo, y0i, kxpi, s_row[r], a1, a2, ps);
+  }
+  if (mode != M_NORMAL) {
+    block_sum_ns(ps, s_red, s_out);
+    if (threadIdx.x < kNS) A.partD[(int64_t)b.gid * kNS + threadIdx.x] = s_out[threadIdx.x];
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
-  __shared__ T s_prod[Tile<T>::NB];
-  __shared__ T s_rsum[3][kMaxRows];
-  __shared__ int s_rp[kMaxRows + 1];
+  __shared__ StepSmem<T> sm;
   __shared__ double s_red[kThreads / 64][kNS];
   __shared__ double s_out[kNS];
+  T* s_prod = sm.p.prod;
+  T (*s_rsum)[kMaxRows] = sm.p.rsum;
+  int* s_rp = sm.p.rp;
 
   const Blk b = A.schedD[blockIdx.x];
   if (blk_kind(b) == BK_PAD) return;
+  if (blk_kind(b) == BK_SORTED) {
+    dual_sorted<T>(A, b, step, sm.rows, s_red, s_out);
+    return;
+  }
   const int nrows = b.r1 - b.r0;
   const int t = threadIdx.x;
   const bool own = t < nrows;
@@ -705,72 +938,9 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
 #pragma unroll
   for (int s = 0; s < kNS; ++s) ps[s] = 0.0;
   if (own) {
-    const bool ineq = (i - S.row0) >= S.m_eq;
-    if (mode == M_EVAL) {
-      const T s0 = s_rsum[0][t];
-      A.kxp[i] = s0;
-      const double dr = A.Dr[i];
-      double r = ((double)s0 - (double)qi) / dr;
-      if (ineq) r = fmin(r, 0.0);
-      ps[0] = r * r;
-      ps[1] = (double)A.dy[i] * ((double)s0 - (double)A.kxbar[i]);
-#pragma unroll
-      for (int a = 1; a <= 2; ++a) {
-        const double av = (double)s_rsum[a][t] / dr;
-        if (ineq) {
-          const double mv = fmin(av, 0.0);
-          ps[2 * a + 1] = mv * mv;
-        } else {
-          ps[2 * a] = av * av;
-        }
-      }
-    } else {
-      const T s0 = s_rsum[0][t];
-      const T sigma = (T)S.sigma;
-      T yp = yo + sigma * (qi - s0);
-      if (ineq) yp = fmax(yp, (T)0);
-      const T yb = (T)2 * yp - yo;
-      const int64_t k = g - S.kbase;
-      T yc = yp;  // check candidate
-      if (S.avg) {
-        const T ysum = (k == 0 ? yo : A.ys[i]) + yp;
-        A.ys[i] = ysum;
-        A.y[i] = yp;
-        if (mode == M_CHECK) yc = ysum / (T)(k + 2);
-      } else {
-        const double w = (double)(k + 1) / (double)(k + 2);
-        const T yh = S.reflect ? yb : yp;
-        A.y[i] = (T)w * yh + (T)(1.0 - w) * y0i;
-      }
-      if (resid) {
-        A.y0[i] = yo;
-        const double d = (double)yo - (double)yp;
-        ps[0] = d * d;
-        ps[1] = d * (0.5 * ((double)kxpi - (double)s0));
-      } else if (mode == M_CHECK) {
-        A.yT[i] = yc;
-        const T dyv = yo - yp;
-        A.dy[i] = dyv;
-        A.kxbar[i] = s0;
-        T e1 = yp - yo, e2 = yo - y0i;
-        if (ineq) {
-          e1 = fmax(e1, (T)0);
-          e2 = fmax(e2, (T)0);
-        }
-        A.cy1[i] = e1;
-        A.cy2[i] = e2;
-        const double ad = (double)yc - (double)y0i;
-        ps[0] = (double)dyv * (double)dyv;
-        ps[1] = ad * ad;
-        ps[2] = (double)qi * (double)yc;
-        ps[3] = (double)qi * (double)e1;
-        ps[4] = (double)qi * (double)e2;
-        const uint8_t act = (ineq && yp == (T)0) ? 1 : 0;
-        const uint8_t was = A.acty[i];
-        A.acty[i] = act;
-        ps[5] = (was != 255 && was != act) ? 1.0 : 0.0;
-      }
-    }
+    const bool eval = (mode == M_EVAL);
+    dual_row<T>(A, S, mode, g, i, qi, yo, y0i, kxpi, s_rsum[0][t], eval ? s_rsum[1][t] : (T)0,
+                eval ? s_rsum[2][t] : (T)0, ps);
   }
   if (mode == M_NORMAL) return;
 
@@ -1187,6 +1357,43 @@ __global__ void slice_keys_kernel(const int32_t* rp, const int32_t* ci, int64_t 
   }
 }
 
+// Column-sorting of plain blocks (BK_SORTED), step 1: for every entry of
+// the block, its sort key (column - b.rp_off) << rb | (row - b.r0) and its
+// position.  Positions are relative to nz0 in the key arrays.
+__global__ __launch_bounds__(kThreads) void sorted_keys_kernel(const Blk* blks, const int32_t* rp,
+                                                               const int32_t* ci, int64_t nz0, uint32_t* key,
+                                                               int32_t* src) {
+  const Blk b = blks[blockIdx.x];
+  const int rb = blk_rowbits(b);
+  const int nrows = b.r1 - b.r0;
+  for (int r = threadIdx.x; r < nrows; r += kThreads) {
+    for (int32_t e = rp[b.r0 + r]; e < rp[b.r0 + r + 1]; ++e) {
+      key[e - nz0] = ((uint32_t)(ci[e] - b.rp_off) << rb) | (uint32_t)r;
+      src[e - nz0] = e;
+    }
+  }
+}
+
+// Step 2 (after the keys are sorted within each block): the block's entries
+// take the sorted keys as packed column indices and the values of the
+// entries they came from (values staged in v_tmp / v64_tmp, relative to nz0).
+template <class V>
+__global__ __launch_bounds__(kThreads) void sorted_block_gather_kernel(const Blk* blks, int64_t nz0,
+                                                                       const uint32_t* key, const int32_t* src,
+                                                                       const V* val, const double* v64,
+                                                                       int32_t* ci_out, V* v_tmp,
+                                                                       double* v64_tmp) {
+  const Blk b = blks[blockIdx.x];
+  for (int e = threadIdx.x; e < b.pn; e += kThreads) {
+    const int64_t p = (int64_t)b.p0 + e;
+    const int64_t rel = p - nz0;
+    const int32_t from = src[rel];
+    ci_out[p] = (int32_t)key[rel];
+    v_tmp[rel] = val[from];
+    if (v64_tmp) v64_tmp[rel] = v64[from];
+  }
+}
+
 // Sorted slicing, step 2 (after the keys are sorted within each block):
 // entry p takes the sorted key as its packed column index and the value of
 // the entry it came from.
@@ -1333,6 +1540,12 @@ template __global__ void dual_slice_step<float, 512>(IterArgs<float>, int);
 template __global__ void dual_slice_step<float, 1024>(IterArgs<float>, int);
 template __global__ void dual_sorted_slice_step<double>(IterArgs<double>, int);
 template __global__ void dual_sorted_slice_step<float>(IterArgs<float>, int);
+template __global__ void sorted_block_gather_kernel<double>(const Blk*, int64_t, const uint32_t*,
+                                                            const int32_t*, const double*, const double*,
+                                                            int32_t*, double*, double*);
+template __global__ void sorted_block_gather_kernel<float>(const Blk*, int64_t, const uint32_t*,
+                                                           const int32_t*, const float*, const double*,
+                                                           int32_t*, float*, double*);
 template __global__ void sorted_gather_kernel<double>(const uint32_t*, const int32_t*, const double*,
                                                       const double*, int64_t, int32_t*, double*, double*);
 template __global__ void sorted_gather_kernel<float>(const uint32_t*, const int32_t*, const float*,
