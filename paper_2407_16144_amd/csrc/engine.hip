@@ -1083,10 +1083,13 @@ void Engine<T>::slice_matrix(int id, bool dual) {
   if (!dual && !spartP) dalloc(&spartP, 3 * kSlices * NS_);
 }
 
+constexpr int64_t kMinSortedBlocks = 64;
+
 // Column-sorted blocks of one LP's K (dual = true) or K^T, for a product
 // that is not column-sliced: rows longer than a plain tile keep a long
 // block; the other rows go to blocks of at most min(sort_rows,
-// kSortRowsPlain) rows and kSortEntries entries whose entries are put in
+// kSortRowsPlain, max(kMaxRows, rows / kMinSortedBlocks)) rows and
+// kSortEntries entries whose entries are put in
 // column order (keys sorted within each block on the device), each column
 // index packed with the entry's row in the block (see blk_rowbits).
 template <class T>
@@ -1105,6 +1108,11 @@ void Engine<T>::sort_blocks(int id, bool dual) {
   while (((int64_t)1 << cb) < width) ++cb;
   if (cb >= 32) return;
   int64_t rows = std::min<int64_t>(std::min<int64_t>(opt_.sort_rows, kSortRowsPlain), (int64_t)1 << (32 - cb));
+  // at least kMinSortedBlocks blocks per product where rows allow (down to
+  // kMaxRows-row blocks): an LP that runs alone at the end of a batch then
+  // still spreads over many workgroups, and a small LP's gathered vector is
+  // small enough that short blocks keep most of the cache-line sharing
+  rows = std::min<int64_t>(rows, std::max<int64_t>(kMaxRows, (nrows + kMinSortedBlocks - 1) / kMinSortedBlocks));
   int rb = 0;
   while (((int64_t)1 << rb) < rows) ++rb;
   std::vector<int32_t> rp(nrows + 1);
