@@ -309,11 +309,13 @@ __device__ __forceinline__ T rec_proj(T d, bool lf, bool uf) {
 // the group share the cache lines of their gathers.  Products go to the LDS
 // row sums s_row by atomic adds, so the order of the additions within a row
 // is not fixed (the last bits of a sum can differ from run to run).
-template <class T, bool NT>
+// U: entries in flight per thread (measured on the large LP: 8 for the
+// slice groups of K, 4 for the blocks of K^T, whose step kernel also holds
+// the epilogue's registers)
+template <class T, bool NT, int U>
 __device__ __forceinline__ void sorted_rows_sum(const Blk& b, const uint32_t* __restrict__ w,
                                                 const T* __restrict__ val, const T* __restrict__ src,
                                                 T* s_row) {
-  constexpr int U = 8;  // entries in flight per thread
   const int rb = blk_rowbits(b);
   const uint32_t rmask = (1u << rb) - 1u;
   const T* srcb = src + b.rp_off;
@@ -421,8 +423,8 @@ __device__ __forceinline__ void sorted_pass(const Blk& b, const int32_t* __restr
   for (int r = threadIdx.x; r < nrows; r += kThreads) s_row[r] = (T)0;
   lds_barrier();
   const uint32_t* w = reinterpret_cast<const uint32_t*>(ci);
-  if (blk_nt(b)) sorted_rows_sum<T, true>(b, w, val, src, s_row);
-  else sorted_rows_sum<T, false>(b, w, val, src, s_row);
+  if (blk_nt(b)) sorted_rows_sum<T, true, 4>(b, w, val, src, s_row);
+  else sorted_rows_sum<T, false, 4>(b, w, val, src, s_row);
   lds_barrier();
 }
 
@@ -633,8 +635,8 @@ __global__ __launch_bounds__(kThreads) void dual_sorted_slice_step(IterArgs<T> A
     const T* src = mode != M_EVAL ? A.xbar : a == 0 ? A.xT : a == 1 ? A.cx1 : A.cx2;
     for (int r = threadIdx.x; r < nrows; r += kThreads) s_row[r] = (T)0;
     lds_barrier();
-    if (blk_nt(b)) sorted_rows_sum<T, true>(b, w, A.K_v, src, s_row);
-    else sorted_rows_sum<T, false>(b, w, A.K_v, src, s_row);
+    if (blk_nt(b)) sorted_rows_sum<T, true, 8>(b, w, A.K_v, src, s_row);
+    else sorted_rows_sum<T, false, 8>(b, w, A.K_v, src, s_row);
     lds_barrier();
     for (int r = threadIdx.x; r < nrows; r += kThreads)
       A.spartD[(int64_t)(a * kSlices + sl) * A.MS + b.r0 + r] = s_row[r];
