@@ -142,7 +142,8 @@ typedef struct {
                                order with fixed-order sums (slice_entries, slice_rows) */
   int sort_rows;            /* rows per column-sorted slice tile, 1..4096 (default 4096;
                                fewer when the slice is wider than 2^(32 - log2 rows));
-                               column-sorted plain blocks take at most 2048 of them */
+                               column-sorted plain blocks take at most 2048 of them, and
+                               at most max(256, rows of the product / 64) */
   int plain_sort;           /* products that are not column-sliced (K^T of the large LP,
                                both products of small LPs): 1 (default) stores the rows of
                                at most 1024 entries in column-sorted blocks of sort_rows
