@@ -189,6 +189,32 @@ def test_rows_longer_than_a_workgroup_tile():
     assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
 
 
+def test_sorted_block_boundaries():
+    """Column-sorted blocks at their limits: a row of exactly 1024 entries
+    (the longest a sorted block takes), one of 1025 (a long block of its
+    own), and a run of 1000-entry rows that splits blocks at 2^16 entries;
+    the trajectory still agrees with the oracle."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(11)
+    n, m_eq, m_ineq = 3000, 100, 40
+    lens = [1024, 1025] + [1000] * (m_eq - 2) + [12] * m_ineq
+    cols = [np.sort(rng.choice(n, L, replace=False)) for L in lens]
+    col = np.concatenate(cols).astype(np.int32)
+    val = rng.standard_normal(col.size)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    xs = rng.uniform(1.0, 9.0, n)
+    kx = sp.csr_matrix((val, col, rp), shape=(m_eq + m_ineq, n)) @ xs
+    rhs = np.concatenate([kx[:m_eq], kx[m_eq:] - rng.uniform(0.0, 1.0, m_ineq)])
+    lp = lpgen.LP(n, m_eq, m_ineq, rp, col, val, rng.standard_normal(n), rhs, np.zeros(n), np.full(n, 10.0))
+    print("case sorted block boundaries", flush=True)
+    P = core.scaled_problem(lp)
+    s, _ = oracle.power_iteration(P.K, 0)
+    res, x, y, _ = _gpu(lp, 0.0, 500, eta=0.9 / s)
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=500, eta=0.9 / s))
+    assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
+    assert _rel(x, ref.x) <= 1e-10 and _rel(y, ref.y) <= 1e-10
+
+
 def test_unsorted_duplicate_columns_are_canonicalised():
     lp = lpgen.tiny(6)
     m = lp.m
