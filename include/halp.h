@@ -109,9 +109,11 @@ typedef struct {
                                bytes (default 2 MiB; < 0 never) */
   double polish_tol;        /* FP32 precision: when the requested tolerance is
                                below this (default 1e-3), solve in FP32 to this
-                               tolerance (or to the stall rule), then continue in
-                               FP64 from the FP32 candidate (same scaling and step)
-                               to the request: lp_solve and lp_batch_solve */
+                               tolerance (or to the stall rule, or for at most a
+                               tenth of max_iter), then continue in FP64 from the
+                               FP32 candidate (same scaling and step) to the request
+                               with the rest of max_iter: lp_solve, lp_batch_solve
+                               and FP32 servers */
   int verbose;              /* k > 0: progress line on stderr every k seconds of a solve */
   int64_t cache_budget_bytes; /* bytes of vectors and matrix tiles meant to stay in the
                                last-level cache between steps (default 208 MiB of the

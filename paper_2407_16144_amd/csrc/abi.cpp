@@ -1,6 +1,7 @@
 // C ABI over the solver engine (see include/halp.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -257,6 +258,11 @@ struct Polish {
   std::vector<halp::Result> first;    // the FP32 phase's result of each polished LP
 };
 
+// Iterations the FP32 phase of a polished solve may take: a tenth of the
+// request's budget (at least 1), so that an LP whose FP32 trajectory
+// converges slowly without stalling still leaves the FP64 phase most of it.
+int64_t fp32_budget(int64_t max_iter) { return std::max<int64_t>(1, max_iter / 10); }
+
 bool polish_wanted(const halp::Result& r, int64_t max_iter) {
   const bool go = r.status == LP_OPTIMAL || r.status == LP_ITER_LIMIT || r.status == LP_NUMERICAL;
   return go && r.iters < max_iter;
@@ -434,7 +440,8 @@ int lp_solve(lp_solver* s, double tol, int64_t max_iter, double time_limit_s) {
     if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
     const double t0 = now_s();
     const bool polish = s->raw && tol < s->opt.polish_tol;
-    s->eng->set_params({s->id}, polish ? s->opt.polish_tol : tol, max_iter, polish ? s->opt.stall_checks : 0);
+    s->eng->set_params({s->id}, polish ? s->opt.polish_tol : tol, polish ? fp32_budget(max_iter) : max_iter,
+                       polish ? s->opt.stall_checks : 0);
     s->eng->run(time_limit_s);
     if (polish) {
       const double left = time_limit_s < 0 ? -1.0 : time_limit_s - (now_s() - t0);
@@ -541,7 +548,8 @@ int lp_batch_solve(lp_batch* b, double tol, int64_t max_iter, double time_limit_
     if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
     const double t0 = now_s();
     const bool polish = !b->raw.empty() && tol < b->opt.polish_tol;
-    b->eng->set_params(b->ids, polish ? b->opt.polish_tol : tol, max_iter, polish ? b->opt.stall_checks : 0);
+    b->eng->set_params(b->ids, polish ? b->opt.polish_tol : tol, polish ? fp32_budget(max_iter) : max_iter,
+                       polish ? b->opt.stall_checks : 0);
     b->eng->run(time_limit_s);
     if (polish) {
       std::vector<const RawLP*> raw;
@@ -818,7 +826,8 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
       for (auto& [t, id] : admit(s, *s->eng, s->queue)) {
         Request& r = s->reqs.at(t);
         const bool polish = s->eng64 && r.tol < s->opt.polish_tol;
-        by_params[{polish ? s->opt.polish_tol : r.tol, r.max_iter, polish ? s->opt.stall_checks : 0}].push_back(id);
+        by_params[{polish ? s->opt.polish_tol : r.tol, polish ? fp32_budget(r.max_iter) : r.max_iter,
+                   polish ? s->opt.stall_checks : 0}].push_back(id);
         r.slot = id;
         s->slot_ticket[id] = t;
       }

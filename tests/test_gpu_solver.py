@@ -372,7 +372,7 @@ def test_fp32_stall_rule_hands_over_to_fp64():
     lp = lpgen.tiny(4)
     print("case fp32 stall", flush=True)
     # an FP32 phase cannot reach a 1e-9 relative KKT error: without the stall
-    # rule it would spend the whole iteration budget and leave no polish
+    # rule it would spend its share of the budget (a tenth) before the polish
     res, x, y, _ = _gpu(lp, 5e-10, 500_000, precision=halp.LP_PREC_FP32, polish_tol=1e-9, stall_checks=20)
     assert res["status"] == halp.LP_OPTIMAL, res
     assert 0 < res["polish_iters"] < res["iters"] < 250_000, res
