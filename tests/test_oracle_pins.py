@@ -515,3 +515,155 @@ def test_iteration_limit_at_check_granularity():
     assert r.iters == 65   # first check: k = 64 of epoch 0, after 65 evaluations of T
     r = oracle.solve(lp, oracle.Options(max_iter=1000, tol=1e-12))
     assert r.status == core.ITER_LIMIT and 1000 <= r.iters <= 1000 + 65
+
+
+# ---------------------------------------------------------------- primal weight and adaptive restart
+
+def _dense_m_norm(K, dx, dy, tau, sigma):
+    """sqrt(z^T M z) with M = [[I/tau, K^T], [K, I/sigma]] assembled as a dense
+    matrix (Section 1.2's PDHG norm, square root restored, y = -y_paper)."""
+    n, m = dx.shape[0], dy.shape[0]
+    Kd = K.toarray()
+    M = np.block([[np.eye(n) / tau, Kd.T], [Kd, np.eye(m) / sigma]])
+    z = np.concatenate([dx, dy])
+    return math.sqrt(max(float(z @ M @ z), 0.0))
+
+
+def _epochs(lp, **kw):
+    """Run the oracle and collect, per epoch, its primal weight (sqrt(sigma/tau)),
+    its anchor z^{n,0}, the state at its first T evaluation and at every check."""
+    ep = []
+
+    def cb(s):
+        if s["k"] == 0:
+            ep.append(dict(n=s["n"], t=s["t"], omega=math.sqrt(s["sigma"] / s["tau"]),
+                           tau=s["tau"], sigma=s["sigma"], x0=s["x0"].copy(), y0=s["y0"].copy(),
+                           first=(s["x"].copy(), s["y"].copy(), s["xp"].copy(), s["yp"].copy()),
+                           checks=[]))
+        elif s["k"] % 64 == 0:
+            ep[-1]["checks"].append((s["k"], s["t"], s["x"].copy(), s["y"].copy(),
+                                     s["xp"].copy(), s["yp"].copy()))
+
+    r = oracle.solve(lp, oracle.Options(callback=cb, **kw))
+    return r, ep
+
+
+def test_primal_weight_starts_at_norm_ratio():
+    """Primal weight "as cuPDLP" (Section 7): omega_0 = ||c~|| / ||q~|| on the
+    rescaled problem, read back from the step sizes tau = eta/omega,
+    sigma = eta*omega of the first epoch; omega_0 = 1 when c = 0."""
+    lp = lpgen.scaled_powerlaw(5, 200, 600)
+    r, ep = _epochs(lp, tol=0.0, max_iter=64)
+    P = r.scaled
+    want = np.linalg.norm(P.Dc * lp.c) / np.linalg.norm(P.Dr * lp.rhs)
+    assert ep[0]["omega"] == pytest.approx(want, rel=1e-13)
+    assert ep[0]["tau"] * ep[0]["sigma"] == pytest.approx(r.eta ** 2, rel=1e-13)
+    assert abs(math.log(want)) > 0.5          # far from the fallback value 1
+    lp0 = lpgen.LP(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, np.zeros(lp.n), lp.rhs,
+                   lp.lb, lp.ub)
+    _, ep0 = _epochs(lp0, tol=0.0, max_iter=64)
+    assert ep0[0]["omega"] == 1.0
+
+
+def test_primal_weight_update_is_geometric_mean():
+    """At each restart the weight moves half way, in log space, toward the ratio
+    of the dual and primal distances between consecutive restart points:
+    omega_{n+1} = sqrt(omega_n * ||y^{n+1,0} - y^{n,0}|| / ||x^{n+1,0} - x^{n,0}||)."""
+    lp = lpgen.scaled_powerlaw(5, 200, 600)
+    r, ep = _epochs(lp, tol=1e-7, max_iter=200_000)
+    assert len(ep) >= 10
+    moved = 0
+    for a, b in zip(ep, ep[1:]):
+        dx = np.linalg.norm(b["x0"] - a["x0"])
+        dy = np.linalg.norm(b["y0"] - a["y0"])
+        want = math.sqrt(a["omega"] * dy / dx)
+        assert b["omega"] == pytest.approx(want, rel=1e-12)
+        moved += abs(math.log(b["omega"] / a["omega"])) > 1e-3
+    assert moved >= 5
+
+
+def test_adaptive_restart_decision_restated():
+    """eq. (adaptive-restart) with checks every 64 steps (Section 3): for
+    n >= 1, a check restarts iff ||z - T z||_M <= ||z^{n,0} - T z^{n,0}||_M / e
+    in the epoch's norm, or (cuPDLP's artificial restart) k >= 0.36 t; the
+    first epoch restarts at its first check.  Both residuals are recomputed
+    here with a dense M; every kind of decision occurs."""
+    lp = lpgen.scaled_powerlaw(5, 200, 600)
+    r, ep = _epochs(lp, tol=1e-7, max_iter=200_000)
+    assert r.status == core.OPTIMAL
+    K = r.scaled.K
+    kinds = {"first": 0, "resid": 0, "artificial": 0, "none": 0}
+    logi = 0
+    for i, e in enumerate(ep):
+        x, y, xp, yp = e["first"]
+        r0 = _dense_m_norm(K, x - xp, y - yp, e["tau"], e["sigma"])
+        for j, (k, t, x, y, xp, yp) in enumerate(e["checks"]):
+            res = _dense_m_norm(K, x - xp, y - yp, e["tau"], e["sigma"])
+            entry = r.log[logi]
+            logi += 1
+            assert entry["t"] == t and entry["r0"] == pytest.approx(r0, rel=1e-10)
+            assert entry["resid"] == pytest.approx(res, rel=1e-10)
+            last = j == len(e["checks"]) - 1
+            if last and i == len(ep) - 1:
+                break                          # the solve ended at this check
+            restarted = last                   # an epoch ends only at a restart
+            if e["n"] == 0:
+                kind = "first" if k == 64 else None
+            elif res <= r0 / math.e:
+                kind = "resid"
+            elif k >= 0.36 * t:
+                kind = "artificial"
+            else:
+                kind = "none"
+            assert restarted == (kind not in ("none", None)), (i, k, res / r0)
+            kinds[kind] += 1
+    assert logi == len(r.log)
+    assert all(v > 0 for v in kinds.values()), kinds
+
+
+def test_restart_references_contract_by_e():
+    """With a fixed norm (no primal-weight update) and restarts only by the
+    residual rule, the restart point is T(z) and T is nonexpansive in the
+    M-norm, so r0 of the next epoch is at most the residual that triggered the
+    restart, which is at most r0 / e: the restart references fall by at least
+    a factor e per epoch (Section 3, the mechanism behind Theorem 2's rate)."""
+    lp = lpgen.scaled_powerlaw(5, 200, 600)
+    r, ep = _epochs(lp, tol=0.0, max_iter=20_000, primal_weight=False, artificial_restart=0.0)
+    K = r.scaled.K
+    r0s = []
+    for e in ep:
+        x, y, xp, yp = e["first"]
+        r0s.append(_dense_m_norm(K, x - xp, y - yp, e["tau"], e["sigma"]))
+    assert len(r0s) >= 5
+    for a, b in zip(r0s[1:], r0s[2:]):        # the first epoch restarts at its first check
+        assert b <= a / math.e * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("which", ["objective", "rhs_and_bounds"])
+def test_trajectory_equivariant_under_data_scaling(which):
+    """Scaling c by a (duals scale by a) or rhs and bounds by a (primals scale
+    by a) maps PDHG iterates onto each other exactly when omega scales with
+    ||c|| / ||q||: omega_0 by a (or 1/a), each update by the same factor, and
+    the M-norm residual ratios that decide restarts are unchanged.  An omega
+    built from the inverse ratio, or a restart test on an unscaled quantity,
+    breaks the map.  a = 4 keeps every product exact."""
+    lp = lpgen.scaled_powerlaw(5, 200, 600)
+    a = 4.0
+    if which == "objective":
+        lp2 = lpgen.LP(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, a * lp.c, lp.rhs, lp.lb, lp.ub)
+        fx, fy = 1.0, a
+    else:
+        lp2 = lpgen.LP(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, lp.c, a * lp.rhs,
+                       a * lp.lb, a * lp.ub)
+        fx, fy = a, 1.0
+    kw = dict(tol=0.0, max_iter=6000)
+    r1, e1 = _epochs(lp, **kw)
+    r2, e2 = _epochs(lp2, **kw)
+    assert r1.restarts >= 5 and r1.restarts == r2.restarts
+    assert [e["t"] for e in e1] == [e["t"] for e in e2]
+    for p, q in zip(e1, e2):
+        assert q["omega"] == pytest.approx(p["omega"] * fy / fx, rel=1e-10)
+    sx = 1 + np.abs(r1.x).max()
+    sy = 1 + np.abs(r1.y).max()
+    assert np.abs(r2.x - fx * r1.x).max() <= 1e-9 * fx * sx
+    assert np.abs(r2.y - fy * r1.y).max() <= 1e-9 * fy * sy
