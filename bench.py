@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: solved LPs/s (and latency) of restarted Halpern PDHG on one MI355X.
 
-A step is one whole solve of a synthetic LP shaped like the paper's large
-MIP-relaxation instances: 150k equality + 50k inequality rows, 1M variables,
-~9.8M nonzeros with power-law row lengths (8..5000) and six decades of row
-scaling, 20% free variables, feasible and bounded by construction.  Inputs
-are resident in HBM (torch tensors) when the timed region starts; each step
-runs lp_create (validation, transpose, scaling, power iteration) and lp_solve
-to a relative KKT error of 1e-4, FP64, r2HPDHG, through the C ABI.
+Default workload: one synthetic LP shaped like the largest of the paper's
+MIP-relaxation instances (>10M nonzeros, Table 1): 375k equality + 125k
+inequality rows, 2M variables, 29.6M nonzeros with power-law row lengths
+(10..5000) and six decades of row scaling, 20% free variables, feasible and
+bounded by construction.  Its matrices and vectors (about 1 GB per iteration
+in FP64) do not fit the 256 MB Infinity Cache, so the sparse products stream
+from HBM.  A step is one whole solve: lp_create (validation, transpose,
+scaling, power iteration, layouts) and lp_solve to a relative KKT error of
+1e-4, r2HPDHG, FP64 by default (--precision fp32: FP32 streams and an FP64
+polish), through the C ABI, with the inputs resident in HBM (torch tensors)
+when the timed region starts.  Other workloads: --workload large (150k + 50k
+rows x 1M variables, 9.8M nonzeros), tiny, batch (512 LPs), serve (Poisson
+arrivals), mps (a file).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: the solver runs on one GPU.
 """
@@ -95,32 +101,81 @@ def measured_traffic(workload, kernel):
     return None if k is None else int(round(k["traffic_bytes"]))
 
 
-def cpu_baseline(lp, eta, gpu_iters, gpu_power_iters, method, budget_s=30.0):
-    """Oracle timed on a bounded sample of the same LP (single process):
-    scaling + one epoch of 65 iterations with the GPU's step size, and ten
-    power iterations; extrapolated to a whole solve with the GPU's iteration
-    and power-iteration counts."""
-    import numpy as np
+def copy_probe(torch, mb):
+    """A plain streaming kernel (y = -x over FP64 vectors of `mb` MB: reads and
+    writes mb MB per launch) timed with HIP events on the current stream: the
+    bandwidth a simple stream reaches on this GPU, as context for the
+    roofline fractions (and the known-size kernel that calibrates the HBM byte
+    counters)."""
+    nel = int(mb * 1e6 / 8)
+    src = torch.ones(nel, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    byts = 2 * nel * 8
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": byts, "ms": round(ms, 4), "GBs": round(byts / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def cpu_model():
+    """The host CPU's model name (the first 'model name' line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(lp, eta, gpu_iters, gpu_power_iters, method, x=None, y=None, gpu_kkt=None):
+    """Oracle timed on a bounded sample of the same LP (one process, one
+    core): one oracle solve of a single epoch (scaling, then 65 iterations at
+    the GPU's step size with one check), timed per phase from the oracle's
+    per-iteration callback, and ten power iterations on the scaled matrix;
+    extrapolated to a whole solve with the GPU's iteration and
+    power-iteration counts.  When the GPU's solution (x, y) is given, the
+    oracle also recomputes its relative KKT error in FP64 (independent of
+    the solver's own reduction)."""
     import oracle
-    from oracle import core
     os.environ.setdefault("OMP_NUM_THREADS", "1")
+    stamps = []
+    cb = lambda s: stamps.append(time.perf_counter())
     t0 = time.perf_counter()
-    P = core.scaled_problem(lp)
-    t_scale = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.power_iteration(P.K, 0, max_iters=10, min_iters=10, rtol=0.0)
-    t_pw = (time.perf_counter() - t0) / 10.0
-    t0 = time.perf_counter()
-    r = oracle.solve(lp, oracle.Options(method=method, tol=0.0, max_iter=64, eta=eta))
-    t_solve = time.perf_counter() - t0
-    t_iter = max(t_solve - t_scale, 1e-9) / r.iters
-    est = t_scale + gpu_power_iters * t_pw + gpu_iters * t_iter
-    return {"value": 1.0 / est, "unit": "LPs/s", "cores": 1, "kind": "oracle",
-            "sample": (f"same LP: scaling ({t_scale:.1f}s) + 10 power iterations "
-                       f"({t_pw:.3f}s each) + {r.iters} iterations ({t_iter:.3f}s each), "
-                       f"extrapolated to the GPU's {gpu_power_iters} power and {gpu_iters} "
-                       f"solver iterations; est. {est:.0f}s per LP"),
-            "seconds_per_iteration": t_iter}
+    r = oracle.solve(lp, oracle.Options(method=method, tol=0.0, max_iter=64, eta=eta, callback=cb))
+    t_end = time.perf_counter()
+    t_setup = stamps[0] - t0                        # scaling, start point and the first T
+    t_iter = (stamps[-1] - stamps[0]) / max(len(stamps) - 1, 1)
+    p0 = time.perf_counter()
+    oracle.power_iteration(r.scaled.K, 0, max_iters=10, min_iters=10, rtol=0.0)
+    t_pw = (time.perf_counter() - p0) / 10.0
+    est = t_setup + gpu_power_iters * t_pw + gpu_iters * t_iter
+    out = {"value": 1.0 / est, "unit": "LPs/s", "cores": 1, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cores": os.cpu_count(),
+           "sample": (f"same LP, one process: scaling + start ({t_setup:.1f}s), {len(stamps)} "
+                      f"iterations ({t_iter:.3f}s each, one check included), 10 power iterations "
+                      f"({t_pw:.3f}s each), measured in {t_end - t0 + 10 * t_pw:.1f}s and extrapolated "
+                      f"to the GPU's {gpu_power_iters} power and {gpu_iters} solver iterations: "
+                      f"est. {est:.0f}s per LP"),
+           "seconds_per_iteration": t_iter}
+    if x is not None and y is not None:
+        kkt, parts = oracle.rel_kkt(lp, x, y)
+        out["oracle_rel_kkt_of_gpu_solution"] = kkt
+        out["oracle_pobj_of_gpu_solution"] = parts["pobj"]
+        if gpu_kkt is not None:
+            out["gpu_reported_rel_kkt"] = gpu_kkt
+    return out
 
 
 def _oracle_rate_worker(args):
@@ -342,14 +397,14 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="r2hpdhg", choices=list(METHODS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2_000_000)
     ap.add_argument("--time-limit", type=float, default=600.0)
-    ap.add_argument("--workload", default="large", choices=["large", "mixed", "tiny", "batch", "serve", "mps"])
+    ap.add_argument("--workload", default="mixed", choices=["large", "mixed", "tiny", "batch", "serve", "mps"])
     ap.add_argument("--mps", default=None, help="workload mps: the LP to solve (.mps or .mps.gz)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--requests", type=int, default=1200)
@@ -388,15 +443,9 @@ def main():
         out = run_batch(args) if args.workload == "batch" else run_serve(args)
         print(json.dumps(out), flush=True)
         return
-    if args.copy_probe_mb > 0:
-        nel = int(args.copy_probe_mb * 1e6 / 8)
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        print(f"copy probe: neg kernel reads and writes {nel * 8} bytes per launch", file=sys.stderr,
-              flush=True)
+    copy = copy_probe(torch, args.copy_probe_mb if args.copy_probe_mb > 0 else 1024.0)
+    print(f"copy probe: {copy['bytes_per_launch']} B per launch at {copy['GBs']:.0f} GB/s", file=sys.stderr,
+          flush=True)
     if args.workload == "mps":
         from paper_2407_16144_amd import mps
         if not args.mps:
@@ -426,19 +475,20 @@ def main():
         **({} if args.cache_budget_mb is None else {"cache_budget_bytes": int(args.cache_budget_mb * 2**20)}),
         **{**_det(args), **tuned})
 
-    def step():
+    def step(keep=False):
         h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *tens, inputs_on_device=1,
                            stream=stream.cuda_stream, opt=opt)
         try:
             halp.lp_solve(h, args.tol, args.max_iter, args.time_limit)
             r = halp.lp_status(h).as_dict()
             kt = halp.lp_kernel_times(h)
+            sol = halp.lp_get_solution(h, lp.n, lp.m) if keep else None
         finally:
             halp.lp_destroy(h)
-        return r, kt
+        return r, kt, sol
 
     for i in range(args.warmup):
-        r, _ = step()
+        r, _, _ = step()
         print(f"warmup {i}: status={halp.STATUS_NAMES[r['status']]} iters={r['iters']} "
               f"kkt={r['rel_kkt']:.2e} t={r['seconds']:.2f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -448,7 +498,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         s0 = time.perf_counter()
-        r, kt = step()
+        r, kt, sol = step(keep=(i == args.steps - 1))
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - s0)
         results.append(r)
@@ -490,7 +540,8 @@ def main():
                 "avg_ms": {names[k]: round(v, 5) for k, v in avg.items()},
                 "bytes": {names[k]: int(v) for k, v in byname.items()},
                 "timed_steps": ksum["steps"], "event_pair_ms": round(ev, 5),
-                "step_achieved_GBs": round(sum(byname.values()) / (tstep * 1e-3) / 1e9, 1) if tstep > 0 else 0}
+                "step_achieved_GBs": round(sum(byname.values()) / (tstep * 1e-3) / 1e9, 1) if tstep > 0 else 0,
+                "copy_kernel": copy}
     lat_sorted = sorted(lat)
     p50 = lat_sorted[len(lat) // 2]
     p99 = lat_sorted[min(len(lat) - 1, math.ceil(0.99 * len(lat)) - 1)]
@@ -515,7 +566,8 @@ def main():
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(lp, results[-1]["eta"], iters,
-                                               results[-1]["power_iters"], args.method)
+                                               results[-1]["power_iters"], args.method,
+                                               x=sol[0], y=sol[1], gpu_kkt=results[-1]["rel_kkt"])
         except Exception as e:  # pragma: no cover
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
