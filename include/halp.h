@@ -304,6 +304,41 @@ int lp_server_clock(const lp_server* s, double* now);
 int lp_server_info(const lp_server* s, int* queued, int* live, int64_t* bytes_in_use);
 void lp_server_destroy(lp_server* s);
 
+/* ---------------------------------------------------------------- no allocation */
+
+/* Bytes of the static device workspace that lp_solve_static draws on: one
+ * array per GPU, part of the library's device code, held by every GPU the
+ * library runs on until the process ends. */
+#define LP_STATIC_WORKSPACE_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc, code that prepares a graph capture):
+ * lp_create + lp_solve + lp_get_solution + lp_destroy of one LP in a single
+ * call that allocates no device memory and no pinned host memory.  Every
+ * device buffer of the solve (the copied LP, K^T, scaled data, iterates,
+ * schedules, partial sums, sort buffers) is carved out of the static
+ * workspace of the current GPU and cleared before use; results equal those
+ * of lp_create + lp_solve with the same options and use_graph = 0.
+ *  - row_ptr .. ub: device pointers, same layout as lp_create (inputs are
+ *    copied; the caller keeps ownership).  x (n) and y (m_eq + m_ineq)
+ *    receive the unscaled candidate of the last check in DEVICE memory;
+ *    either may be NULL.  *out receives the status and statistics.
+ *  - stream: a hipStream_t, or NULL for the null stream; the call returns
+ *    after its work on the stream has finished.
+ *  - FP64 only: opt->precision must be LP_PREC_FP64 (LP_ERR_INVALID
+ *    otherwise); opt->use_graph and opt->profile are ignored (no graphs,
+ *    no events).
+ *  - LP_ERR_OOM, with the bytes needed in lp_last_error(), when the LP does
+ *    not fit LP_STATIC_WORKSPACE_BYTES (roughly up to 1M stored entries);
+ *    the check happens before any buffer beyond the workspace would be used.
+ *  - All calls on one GPU share that GPU's workspace, which keeps the last
+ *    call's contents: two calls overlapping on one GPU would race, so the
+ *    library serialises the calls of a process with a lock. */
+int lp_solve_static(int64_t n, int64_t m_eq, int64_t m_ineq, const int32_t* row_ptr, const int32_t* col_idx,
+                    const double* val, const double* c, const double* rhs, const double* lb, const double* ub,
+                    void* stream, const lp_options* opt, double rel_kkt_tol, int64_t max_iter,
+                    double time_limit_s, double* x, double* y, lp_result* out);
+
 #ifdef __cplusplus
 }
 #endif

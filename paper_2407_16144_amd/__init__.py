@@ -106,6 +106,8 @@ _sig = {
     "lp_server_clock": (C.c_int, [_P, _P]),
     "lp_server_info": (C.c_int, [_P, _P, _P, _P]),
     "lp_server_destroy": (None, [_P]),
+    "lp_solve_static": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                  C.c_double, C.c_int64, C.c_double, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -347,6 +349,30 @@ def lp_server_info(h):
 
 def lp_server_destroy(h):
     _lib.lp_server_destroy(h)
+
+
+LP_STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def lp_solve_static(n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub, rel_kkt_tol, max_iter,
+                    time_limit_s=-1.0, x=None, y=None, stream=None, opt=None) -> lp_result:
+    """The allocation-free solve: device tensors in, the unscaled solution
+    written into the device tensors x (n) and y (m) when given."""
+    ptrs, keep = _marshal_problem(n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub, 1)
+    for a in (x, y):
+        if a is not None and (a.dtype != torch.float64 or not a.is_contiguous() or not a.is_cuda):
+            raise TypeError("x and y must be contiguous float64 device tensors")
+    if x is not None and x.numel() < n:
+        raise ValueError("x holds fewer than n entries")
+    if y is not None and y.numel() < m_eq + m_ineq:
+        raise ValueError("y holds fewer than m entries")
+    r = lp_result()
+    _check(_lib.lp_solve_static(n, m_eq, m_ineq, *ptrs, stream, C.byref(opt) if opt is not None else None,
+                                float(rel_kkt_tol), int(max_iter), float(time_limit_s),
+                                None if x is None else x.data_ptr(), None if y is None else y.data_ptr(),
+                                C.byref(r)))
+    del keep
+    return r
 
 
 def solve_lp(lp, tol=1e-4, max_iter=1_000_000, time_limit=-1.0, opt=None, on_device=False,

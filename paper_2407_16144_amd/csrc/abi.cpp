@@ -7,6 +7,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -503,6 +504,47 @@ void lp_destroy(lp_solver* s) {
     delete s;
   } catch (...) {
   }
+}
+
+// ------------------------------------------------------------------ no allocation
+
+int lp_solve_static(int64_t n, int64_t m_eq, int64_t m_ineq, const int32_t* row_ptr, const int32_t* col_idx,
+                    const double* val, const double* c, const double* rhs, const double* lb, const double* ub,
+                    void* stream, const lp_options* opt, double tol, int64_t max_iter, double time_limit_s,
+                    double* x, double* y, lp_result* out) {
+  static std::mutex mu;  // one workspace per GPU: calls of this process take turns
+  return guarded([&]() -> int {
+    if (!out) return fail(LP_ERR_INVALID, "null result");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(LP_ERR_INVALID, "need tol >= 0 and max_iter >= 1");
+    halp::Options o = to_opts(opt);
+    check_opts(o);
+    if (o.precision != 0) return fail(LP_ERR_INVALID, "lp_solve_static solves in FP64 only");
+    o.use_graph = 0;
+    o.profile = 0;
+    lp_problem p{n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub};
+    const int64_t nnz = read_nnz(p, true);
+    const int64_t m = m_eq + m_ineq;
+    // K and K^T (indices and FP64 values) alone need 24 bytes per entry
+    const int64_t floor_bytes = 24 * nnz + 8 * (m + n);
+    if (floor_bytes > halp::kWorkspaceBytes)
+      return fail(LP_ERR_OOM, "LP too large for the static workspace: at least " + std::to_string(floor_bytes) +
+                                  " bytes needed of " + std::to_string((long long)halp::kWorkspaceBytes));
+    std::lock_guard<std::mutex> lk(mu);
+    hipStream_t st = (hipStream_t)stream;
+    const double t0 = now_s();
+    halp::WorkspaceScope ws(st);
+    {
+      std::unique_ptr<halp::EngineBase> eng = halp::make_engine(o, st, m + 1, n + 1, nnz, 1);
+      const int id = eng->add({to_problem(p)}, true)[0];
+      eng->set_params({id}, tol, max_iter, 0);
+      eng->run(time_limit_s);
+      const halp::Result r = eng->result(id);
+      if (x || y) eng->solution(id, x, y, true);
+      *out = to_result(r, now_s() - t0);
+    }
+    hip_ok(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return LP_OK;
+  });
 }
 
 // ------------------------------------------------------------------ batch

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "halp.h"
 #include "halp_types.h"
 
 namespace halp {
@@ -127,6 +128,22 @@ class EngineBase {
   // start the next solve of `id` from (x, y) (scaled, float64 device arrays)
   // with primal weight omega: iterate and anchor both set to the point
   virtual void import_point(int id, const double* x, const double* y, double omega) = 0;
+};
+
+// Size of the static device workspace of the allocation-free entry point.
+constexpr int64_t kWorkspaceBytes = LP_STATIC_WORKSPACE_BYTES;
+
+// While a WorkspaceScope is alive on a thread, every device buffer that an
+// engine created on that thread allocates comes from the static workspace of
+// the current device (no hipMalloc), cleared to zero on `stream`; engines
+// created in the scope must be destroyed before it ends.  Scopes do not nest.
+class WorkspaceScope {
+ public:
+  explicit WorkspaceScope(hipStream_t stream);
+  ~WorkspaceScope();
+  WorkspaceScope(const WorkspaceScope&) = delete;
+  WorkspaceScope& operator=(const WorkspaceScope&) = delete;
+  size_t peak() const;  // most bytes in use at once so far
 };
 
 // Host-side validation of a host-memory LP (throws Error(-1, ...)); needs no GPU.

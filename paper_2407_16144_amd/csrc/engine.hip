@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -72,19 +73,106 @@ class RangeAlloc {
   std::map<int64_t, int64_t> free_;
 };
 
+// ---------------------------------------------------------------------------
+// device memory
+//
+// Every buffer of an engine comes from dalloc.  Normally that is hipMalloc;
+// inside a WorkspaceScope (the allocation-free entry point) the buffers are
+// carved out of `scratch`, a static device array, by a stack allocator: a
+// freed block is reclaimed once every block above it is freed too (the
+// engine frees its temporaries in the reverse order of their allocation).
+// Carved blocks are cleared to zero on the workspace's stream, as fresh
+// device memory would be.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) char scratch[kWorkspaceBytes];
+
+struct Workspace {
+  char* base = nullptr;    // this device's copy of `scratch` (from hipGetSymbolAddress)
+  size_t used = 0, peak = 0;
+  hipStream_t stream = nullptr;
+  std::vector<std::pair<size_t, bool>> blocks;  // (offset, freed) in allocation order
+};
+static thread_local Workspace* t_ws = nullptr;
+
+// Address of this device's copy of `scratch`; looked up once per device with
+// that device current (the array's host-side name is not a device address).
+static char* scratch_base(int device) {
+  static std::mutex mu;
+  static std::map<int, char*> base;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = base.find(device);
+  if (it != base.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    throw Error(-3, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+  base[device] = (char*)p;
+  return (char*)p;
+}
+
+static void* ws_alloc(size_t bytes) {
+  Workspace& w = *t_ws;
+  const size_t b = (bytes + 255) & ~size_t(255);
+  if (w.used + b > (size_t)kWorkspaceBytes)
+    throw Error(-2, "static workspace exhausted: " + std::to_string(w.used + b) + " bytes needed of " +
+                        std::to_string((long long)kWorkspaceBytes));
+  char* p = w.base + w.used;
+  w.blocks.push_back({w.used, false});
+  w.used += b;
+  w.peak = std::max(w.peak, w.used);
+  const hipError_t e = hipMemsetAsync(p, 0, b, w.stream);
+  if (e != hipSuccess) throw Error(-3, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+  return p;
+}
+
+static bool ws_free(void* p) {
+  Workspace* w = t_ws;
+  if (!w || (char*)p < w->base || (char*)p >= w->base + kWorkspaceBytes) return false;
+  const size_t off = (size_t)((char*)p - w->base);
+  for (auto& bl : w->blocks)
+    if (bl.first == off) bl.second = true;
+  while (!w->blocks.empty() && w->blocks.back().second) {
+    w->used = w->blocks.back().first;
+    w->blocks.pop_back();
+  }
+  return true;
+}
+
 template <class P>
 static void dalloc(P** p, int64_t count) {
   *p = nullptr;
   if (count <= 0) count = 1;
+  if (t_ws) {
+    *p = (P*)ws_alloc(sizeof(P) * (size_t)count);
+    return;
+  }
   hipError_t e = hipMalloc((void**)p, sizeof(P) * (size_t)count);
   if (e != hipSuccess) throw Error(-2, std::string("device allocation failed: ") + hipGetErrorString(e));
 }
 
 template <class P>
 static void dfree(P*& p) {
-  if (p) (void)hipFree((void*)p);
+  if (p && !ws_free((void*)p)) (void)hipFree((void*)p);
   p = nullptr;
 }
+
+WorkspaceScope::WorkspaceScope(hipStream_t stream) {
+  if (t_ws) throw Error(-4, "nested use of the static workspace");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) throw Error(-3, "hipGetDevice failed");
+  std::unique_ptr<Workspace> w(new Workspace());
+  w->base = scratch_base(dev);
+  w->stream = stream;
+  t_ws = w.release();
+}
+
+WorkspaceScope::~WorkspaceScope() {
+  delete t_ws;
+  t_ws = nullptr;
+}
+
+size_t WorkspaceScope::peak() const { return t_ws ? t_ws->peak : 0; }
 
 // Workgroup schedule of one LP's rows: consecutive rows are packed into
 // "stream" blocks of at most NB entries and kMaxRows rows; a row with more
@@ -336,6 +424,7 @@ class Engine final : public EngineBase {
   double *partP = nullptr, *partD = nullptr;
   int* h_status[2] = {nullptr, nullptr};
   hipEvent_t ev_[2] = {nullptr, nullptr};
+  bool ws_ = false;  // buffers come from the static workspace (no events, no pinned memory)
   bool sched_dirty_ = true;
   hipGraphExec_t gexec_ = nullptr;
   hipGraph_t graph_ = nullptr;
@@ -392,10 +481,16 @@ void Engine<T>::allocate() {
   HIPCHECK(hipGetLastError());
   const int64_t gb = -(int64_t)opt_.chunk;
   HIPCHECK(hipMemcpyAsync(d_gbase, &gb, sizeof(int64_t), hipMemcpyHostToDevice, stream_));
+  ws_ = t_ws != nullptr;
   for (int i = 0; i < 2; ++i) {
-    HIPCHECK(hipHostMalloc((void**)&h_status[i], sizeof(int) * nslots_, hipHostMallocDefault));
+    if (ws_) {
+      // static workspace: ordinary host memory, status reads synchronise the stream
+      h_status[i] = new int[nslots_];
+    } else {
+      HIPCHECK(hipHostMalloc((void**)&h_status[i], sizeof(int) * nslots_, hipHostMallocDefault));
+      HIPCHECK(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
+    }
     std::memset(h_status[i], 0, sizeof(int) * nslots_);
-    HIPCHECK(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
   }
   h_st_.resize(nslots_);
   HIPCHECK(hipStreamSynchronize(stream_));
@@ -444,7 +539,10 @@ void Engine<T>::release_all() {
   dfree(partP);
   dfree(partD);
   for (int i = 0; i < 2; ++i) {
-    if (h_status[i]) (void)hipHostFree(h_status[i]);
+    if (h_status[i]) {
+      if (ws_) delete[] h_status[i];
+      else (void)hipHostFree(h_status[i]);
+    }
     h_status[i] = nullptr;
     if (ev_[i]) (void)hipEventDestroy(ev_[i]);
     ev_[i] = nullptr;
@@ -599,8 +697,8 @@ void Engine<T>::transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1,
     size_t tmp_bytes = 0;
     HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, K_ci + z0, keys, vin, vout, (int)nnz, 0,
                                                 end_bit, stream_));
-    void* tmp = nullptr;
-    HIPCHECK(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
+    char* tmp = nullptr;
+    dalloc(&tmp, (int64_t)tmp_bytes);
     HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, K_ci + z0, keys, vin, vout, (int)nnz, 0,
                                                 end_bit, stream_));
     transpose_gather_kernel<double><<<nblk(nnz), 256, 0, stream_>>>(vout, rowid, K_v64, z0, nnz, KT_ci,
@@ -608,7 +706,7 @@ void Engine<T>::transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1,
     transpose_rowptr_kernel<<<nblk(c1 - c0 + 1), 256, 0, stream_>>>(keys, nnz, z0, c0, c1, KT_rp);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(stream_));
-    (void)hipFree(tmp);
+    dfree(tmp);
     dfree(rowid);
     dfree(keys);
     dfree(vin);
@@ -1182,8 +1280,8 @@ void Engine<T>::sort_blocks(int id, bool dual) {
     size_t tmp_bytes = 0;
     HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tmp_bytes, key_in, key_out, src_in, src_out,
                                                          (int)nnz, nseg, d_b, d_e, 0, 32, stream_));
-    void* tmp = nullptr;
-    HIPCHECK(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
+    char* tmp = nullptr;
+    dalloc(&tmp, (int64_t)tmp_bytes);
     HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, src_in, src_out,
                                                          (int)nnz, nseg, d_b, d_e, 0, 32, stream_));
     sorted_block_gather_kernel<T><<<(unsigned)nseg, kThreads, 0, stream_>>>(d_blk, S.nz0, key_out, src_out, val,
@@ -1193,7 +1291,7 @@ void Engine<T>::sort_blocks(int id, bool dual) {
     if (v64_tmp)
       HIPCHECK(hipMemcpyAsync(v64 + S.nz0, v64_tmp, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
     HIPCHECK(hipStreamSynchronize(stream_));
-    (void)hipFree(tmp);
+    dfree(tmp);
     dfree(d_blk);
     dfree(d_b);
     dfree(d_e);
@@ -1320,8 +1418,8 @@ void Engine<T>::slice_sorted(int id) {
   size_t tmp_bytes = 0;
   HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tmp_bytes, key_in, key_out, src_in, src_out,
                                                        (int)nnz, nseg, d_off, d_off + 1, 0, 32, stream_));
-  void* tmp = nullptr;
-  HIPCHECK(hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1));
+  char* tmp = nullptr;
+  dalloc(&tmp, (int64_t)tmp_bytes);
   HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, src_in, src_out,
                                                        (int)nnz, nseg, d_off, d_off + 1, 0, 32, stream_));
   sorted_gather_kernel<T><<<nblk(nnz), 256, 0, stream_>>>(key_out, src_out, K_v, K_v64, nnz, K_ci + S.nz0, v2,
@@ -1330,7 +1428,7 @@ void Engine<T>::slice_sorted(int id) {
   HIPCHECK(hipMemcpyAsync(K_v + S.nz0, v2, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
   if (v642) HIPCHECK(hipMemcpyAsync(K_v64 + S.nz0, v642, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
   HIPCHECK(hipStreamSynchronize(stream_));
-  (void)hipFree(tmp);
+  dfree(tmp);
   dfree(d_dst);
   dfree(d_rloc);
   dfree(d_off);
@@ -1663,9 +1761,10 @@ void Engine<T>::run(double time_limit_s) {
   while (true) {
     launch_chunk();
     HIPCHECK(hipMemcpyAsync(h_status[j & 1], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost, stream_));
-    HIPCHECK(hipEventRecord(ev_[j & 1], stream_));
+    if (ev_[j & 1]) HIPCHECK(hipEventRecord(ev_[j & 1], stream_));
+    else HIPCHECK(hipStreamSynchronize(stream_));
     if (j >= 1) {
-      HIPCHECK(hipEventSynchronize(ev_[(j - 1) & 1]));
+      if (ev_[(j - 1) & 1]) HIPCHECK(hipEventSynchronize(ev_[(j - 1) & 1]));
       if (all_done(h_status[(j - 1) & 1])) break;
       // leave finished LPs out of the schedules once half of them are done
       int running = 0;
