@@ -152,8 +152,10 @@ def m_norm(P: ScaledLP, dx, dy, tau, sigma):
     """||(dx, dy)||_M with M = [[I/tau, K^T], [K, I/sigma]]: the PDHG norm of
     Section 1.2 with the square root restored, tau = eta/omega and
     sigma = eta*omega, and the off-diagonal sign that goes with y = -y_paper."""
-    v = float(dx @ dx) / tau + float(dy @ dy) / sigma + 2.0 * float(dy @ (P.K @ dx))
-    return math.sqrt(max(v, 0.0))
+    with np.errstate(all="ignore"):   # IEEE results (inf, nan) instead of exceptions
+        v = (np.float64(dx @ dx) / np.float64(tau) + np.float64(dy @ dy) / np.float64(sigma)
+             + 2.0 * np.float64(dy @ (P.K @ dx)))
+        return float(np.sqrt(np.maximum(v, 0.0))) if not np.isnan(v) else float("nan")
 
 
 class _Activity:
