@@ -106,7 +106,8 @@ typedef struct {
                                events on the solver's stream (see lp_kernel_times) */
   int64_t slice_min_bytes;  /* store K (K^T) column-sliced, one slice per XCD, when
                                the vector its product gathers exceeds this many
-                               bytes (default 2 MiB; < 0 never) */
+                               bytes (default 6 MiB, above the 4 MB L2 of one
+                               XCD; < 0 never) */
   double polish_tol;        /* FP32 precision: when the requested tolerance is
                                below this (default 1e-3), solve in FP32 to this
                                tolerance (or to the stall rule, or for at most a
@@ -142,15 +143,26 @@ typedef struct {
                                the order of the additions within a row, and so the last
                                bits of the iterates, may differ from run to run); 0: rows in
                                order with fixed-order sums (slice_entries, slice_rows) */
-  int sort_rows;            /* rows per column-sorted slice tile, 1..4096 (default 4096;
-                               fewer when the slice is wider than 2^(32 - log2 rows));
-                               column-sorted plain blocks take at most 2048 of them, and
-                               at most max(256, rows of the product / 64) */
+  int sort_rows;            /* most rows per sorted group, 1..16384 (default 16384): the
+                               engine takes the largest group that leaves at least 480
+                               workgroups per product and fits the packed column index
+                               (fewer rows when a slice is wider than
+                               2^(32 - log2 rows)); column-sorted plain blocks take at
+                               most 2048 of them, and at most max(256, rows / 64) */
   int plain_sort;           /* products that are not column-sliced (K^T of the large LP,
                                both products of small LPs): 1 (default) stores the rows of
                                at most 1024 entries in column-sorted blocks of sort_rows
                                (<= 2048) rows with LDS-atomic row sums (same caveat as
                                slice_sort); 0: plain tiles (tile_rows) with fixed-order sums */
+  int group_threads;        /* threads per workgroup of the sorted-group slice kernels:
+                               256, 512 or 1024; 0 (default): enough for about eight
+                               waves per CU over the product's workgroups */
+  int group_batched;        /* 1 (default): each thread issues the gathers of a batch of
+                               entries together, then adds them into the LDS row sums;
+                               0: one gather per add */
+  int group_blocks;         /* fewest workgroups a product stored in sorted groups is cut
+                               into (default 240, about one per CU): groups get as many
+                               rows as that allows */
 } lp_options;
 
 typedef struct {
@@ -280,7 +292,14 @@ typedef struct lp_server lp_server;
  * admitted when a slot and enough of the reserved device memory are free,
  * advance together with every other live LP, and retire as soon as they
  * finish (results are copied to host memory and their memory is reused).
- * hbm_budget_bytes bounds the device memory reserved for LP data. */
+ * hbm_budget_bytes bounds the device memory the server allocates: FP32
+ * servers give half of it to the FP32 engine and half to the FP64 polish
+ * engine (with its staging buffer); of each half, three quarters hold the
+ * live LPs and one quarter the transient buffers of an admission (about 48
+ * bytes per stored entry of the LPs admitted in one step, which caps how
+ * much one step admits).  Served LPs are never column-sliced
+ * (opt->slice_min_bytes is ignored), so no buffer is allocated while
+ * serving beyond the small workgroup schedules. */
 int lp_server_create(lp_server** out, int64_t hbm_budget_bytes, int max_slots, void* stream,
                      const lp_options* opt);
 /* Copies the LP (host arrays) into the queue; *ticket identifies it.

@@ -329,7 +329,7 @@ def solve(lp, opts: Options | None = None) -> Result:
                          margin=abs(res - opts.restart_beta * r0) / r0 if r0 > 0 else float("inf"),
                          active_changes=act.update(P, lp.m_eq, xp, yp, t))
             log.append(entry)
-            if not np.isfinite(kkt) or not np.isfinite(res):
+            if not all(np.isfinite(v) for v in (kkt, res, parts["primal"], parts["dual"], parts["gap"])):
                 return finish(NUMERICAL, xp, yp)
             if kkt <= opts.tol:
                 return finish(OPTIMAL, xp, yp)
@@ -425,7 +425,7 @@ def _solve_average(lp, opts, P, K0, eta, sigma_hat, piters, omega, x, y) -> Resu
                          margin=min((abs(kkt - v) / v for v in thr), default=float("inf")),
                          active_changes=act.update(P, lp.m_eq, xp, yp, t))
             log.append(entry)
-            if not np.isfinite(kkt):
+            if not all(np.isfinite(v) for v in (kkt, parts["primal"], parts["dual"], parts["gap"])):
                 return finish(NUMERICAL, xa, ya)
             if kkt <= opts.tol:
                 return finish(OPTIMAL, xa, ya)

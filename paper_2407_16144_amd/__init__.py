@@ -47,7 +47,8 @@ class lp_options(C.Structure):
                 ("verbose", C.c_int), ("cache_budget_bytes", C.c_int64), ("stall_checks", C.c_int64),
                 ("restart_mode", C.c_int), ("fixed_restart_len", C.c_int64), ("xcd_pin", C.c_int),
                 ("tile_rows", C.c_int), ("slice_entries", C.c_int), ("slice_rows", C.c_int),
-                ("slice_sort", C.c_int), ("sort_rows", C.c_int), ("plain_sort", C.c_int)]
+                ("slice_sort", C.c_int), ("sort_rows", C.c_int), ("plain_sort", C.c_int),
+                ("group_threads", C.c_int), ("group_batched", C.c_int), ("group_blocks", C.c_int)]
 
 
 class lp_result(C.Structure):

@@ -75,6 +75,9 @@ halp::Options to_opts(const lp_options* o) {
   r.slice_sort = o->slice_sort;
   r.sort_rows = o->sort_rows;
   r.plain_sort = o->plain_sort;
+  r.group_threads = o->group_threads;
+  r.group_batched = o->group_batched;
+  r.group_blocks = o->group_blocks;
   return r;
 }
 
@@ -87,7 +90,11 @@ void check_opts(const halp::Options& o) {
   if (o.slice_sort < 0 || o.slice_sort > 1) throw halp::Error(LP_ERR_INVALID, "slice_sort must be 0 or 1");
   if (o.plain_sort < 0 || o.plain_sort > 1) throw halp::Error(LP_ERR_INVALID, "plain_sort must be 0 or 1");
   if (o.sort_rows < 1 || o.sort_rows > halp::kSortRows)
-    throw halp::Error(LP_ERR_INVALID, "sort_rows must be in 1..4096");
+    throw halp::Error(LP_ERR_INVALID, "sort_rows must be in 1..16384");
+  if (o.group_threads != 0 && o.group_threads != 256 && o.group_threads != 512 && o.group_threads != 1024)
+    throw halp::Error(LP_ERR_INVALID, "group_threads must be 0, 256, 512 or 1024");
+  if (o.group_batched < 0 || o.group_batched > 1) throw halp::Error(LP_ERR_INVALID, "group_batched must be 0 or 1");
+  if (o.group_blocks < 0) throw halp::Error(LP_ERR_INVALID, "group_blocks must be >= 0");
   if (o.restart_mode == 1 && o.fixed_restart_len < 1)
     throw halp::Error(LP_ERR_INVALID, "fixed restarts need fixed_restart_len >= 1");
   if (o.method < 0 || o.method > 2) throw halp::Error(LP_ERR_INVALID, "method must be 0, 1 or 2");
@@ -405,6 +412,9 @@ void lp_default_options(lp_options* o) {
   o->slice_sort = d.slice_sort;
   o->sort_rows = d.sort_rows;
   o->plain_sort = d.plain_sort;
+  o->group_threads = d.group_threads;
+  o->group_batched = d.group_batched;
+  o->group_blocks = d.group_blocks;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }
@@ -698,16 +708,30 @@ halp::Problem request_problem(const Request& r) {
 
 // engine capacities for a memory budget: the budget is split over the three
 // spaces for a reference mix of n = 4 m and nnz = 36 m (the batched sizes)
-bool server_caps(int64_t budget, int precision, int64_t* cap_m, int64_t* cap_n, int64_t* cap_nz) {
+// Capacities of one server engine from its share of the budget: three
+// quarters for the persistent storage of live LPs (per row, per variable and
+// per stored entry as the engine allocates them; `staging`: plus the FP64
+// phase's staging of one candidate, 8 bytes per row and variable), one
+// quarter for the transient buffers of an admission (transpose and layout
+// sorts, about kAdmitBytesPerEntry per stored entry of the LPs admitted in
+// one step).  Servers never column-slice a product, so no slice partial
+// sums are allocated.
+constexpr int64_t kAdmitBytesPerEntry = 48;
+
+bool server_caps(int64_t share, int precision, bool staging, int64_t* cap_m, int64_t* cap_n, int64_t* cap_nz,
+                 int64_t* admit_nz) {
   const int64_t sz = precision == 1 ? 4 : 8;
-  const int64_t per_row = 4 + 24 + 12 * sz, per_col = 4 + 40 + 13 * sz;
+  // as the engine allocates them without slice row pointers (see footprint())
+  const int64_t per_row = 4 + 24 + 12 * sz + 1 + (staging ? 8 : 0);
+  const int64_t per_col = 4 + 40 + 13 * sz + 1 + (staging ? 8 : 0);
   const int64_t per_nz = 24 + (precision == 1 ? 8 : 0);
   const int64_t unit = per_row + 4 * per_col + 36 * per_nz;
-  const int64_t u = budget / unit;
+  const int64_t u = (share / 4 * 3) / unit;
   if (u < 16) return false;
   *cap_m = u;
   *cap_n = 4 * u;
   *cap_nz = std::min<int64_t>(36 * u, INT32_MAX - 1);
+  *admit_nz = std::max<int64_t>(1, (share / 4) / kAdmitBytesPerEntry);
   return true;
 }
 
@@ -729,20 +753,16 @@ struct lp_server {
   std::map<int, int64_t> slot_ticket64;
   double* dbuf = nullptr;  // device staging of candidates between the phases
   int64_t dbuf_len = 0;
+  int64_t admit_nz = 0, admit_nz64 = 0;  // stored entries one admission may add to each engine
   double t0 = 0.0;
   double clock() const { return now_s() - t0; }
   ~lp_server() {
     if (dbuf) (void)hipFree(dbuf);
   }
+  // the staging buffer is allocated with the server, sized for the largest
+  // LP the FP64 engine can hold
   double* staging(int64_t len) {
-    if (len > dbuf_len) {
-      if (dbuf) (void)hipFree(dbuf);
-      dbuf = nullptr;
-      dbuf_len = 0;
-      if (hipMalloc((void**)&dbuf, sizeof(double) * len) != hipSuccess)
-        throw halp::Error(LP_ERR_OOM, "device allocation failed");
-      dbuf_len = len;
-    }
+    if (len > dbuf_len) throw halp::Error(LP_ERR_STATE, "staging buffer too small");
     return dbuf;
   }
 };
@@ -758,17 +778,27 @@ int lp_server_create(lp_server** out, int64_t budget, int max_slots, void* strea
     std::unique_ptr<lp_server> s(new lp_server());
     s->stream.init(stream);
     s->opt = o;
+    // FP32 servers split the budget between the FP32 engine and the FP64
+    // polish engine; served LPs are never column-sliced (no partial-sum
+    // buffers that an admission would have to allocate)
+    s->opt.slice_min_bytes = -1;
+    const bool two = o.precision == 1 && o.polish_tol > 0.0;
+    const int64_t share = two ? budget / 2 : budget;
     int64_t cm = 0, cn = 0, cz = 0;
-    if (!server_caps(budget, o.precision, &cm, &cn, &cz)) return fail(LP_ERR_INVALID, "budget too small");
+    if (!server_caps(share, o.precision, false, &cm, &cn, &cz, &s->admit_nz))
+      return fail(LP_ERR_INVALID, "budget too small");
     s->budget = budget;
     s->max_slots = max_slots;
-    s->eng = halp::make_engine(o, s->stream.s, cm + max_slots, cn + max_slots, cz, max_slots);
-    if (o.precision == 1 && o.polish_tol > 0.0) {
-      // the FP64 phase gets the same budget
-      halp::Options o64 = o;
+    s->eng = halp::make_engine(s->opt, s->stream.s, cm + max_slots, cn + max_slots, cz, max_slots);
+    if (two) {
+      halp::Options o64 = s->opt;
       o64.precision = 0;
-      if (!server_caps(budget, 0, &cm, &cn, &cz)) return fail(LP_ERR_INVALID, "budget too small");
+      if (!server_caps(share, 0, true, &cm, &cn, &cz, &s->admit_nz64))
+        return fail(LP_ERR_INVALID, "budget too small");
       s->eng64 = halp::make_engine(o64, s->stream.s, cm + max_slots, cn + max_slots, cz, max_slots);
+      s->dbuf_len = cm + cn + 2 * max_slots;
+      if (hipMalloc((void**)&s->dbuf, sizeof(double) * s->dbuf_len) != hipSuccess)
+        return fail(LP_ERR_OOM, "device allocation failed");
     }
     s->t0 = now_s();
     *out = s.release();
@@ -806,9 +836,9 @@ int lp_server_submit(lp_server* s, const lp_problem* p, double tol, int64_t max_
     r.t_arrival = t_arrival;
     // refused at once if it would not fit even an idle server (it would
     // otherwise block the head of the queue for good)
-    if (!s->eng->fits_empty(r.n, m, nnz))
+    if (!s->eng->fits_empty(r.n, m, nnz) || nnz > s->admit_nz)
       return fail(LP_ERR_INVALID, "LP is larger than the server's reserved memory");
-    if (s->eng64 && tol < s->opt.polish_tol && !s->eng64->fits_empty(r.n, m, nnz))
+    if (s->eng64 && tol < s->opt.polish_tol && (!s->eng64->fits_empty(r.n, m, nnz) || nnz > s->admit_nz64))
       return fail(LP_ERR_INVALID, "LP is larger than the server's reserved memory (FP64 phase)");
     *ticket = r.ticket;
     s->queue.push_back(r.ticket);
@@ -838,14 +868,21 @@ void finish_request(lp_server* s, Request& r, halp::EngineBase& eng, int slot, c
   std::vector<double>().swap(r.py);
 }
 
-// admits the longest prefix of `queue` that fits `eng` (preprocessed together)
-std::vector<std::pair<int64_t, int>> admit(lp_server* s, halp::EngineBase& eng, std::deque<int64_t>& queue) {
+// admits the longest prefix of `queue` that fits `eng` (preprocessed
+// together), at most admit_nz stored entries at a time (the transient
+// buffers of an admission are sized by them)
+std::vector<std::pair<int64_t, int>> admit(lp_server* s, halp::EngineBase& eng, std::deque<int64_t>& queue,
+                                           int64_t admit_nz) {
   std::vector<std::pair<int64_t, int>> out;
   if (queue.empty() || eng.live() >= s->max_slots) return out;
   std::vector<halp::Problem> ps;
+  int64_t nz = 0;
   for (int64_t t : queue) {
     if ((int)ps.size() >= s->max_slots - eng.live()) break;
-    ps.push_back(request_problem(s->reqs.at(t)));
+    const Request& r = s->reqs.at(t);
+    if (!ps.empty() && nz + r.nnz > admit_nz) break;
+    nz += r.nnz;
+    ps.push_back(request_problem(r));
   }
   std::vector<int> ids = eng.add(ps, false, true);
   for (size_t k = 0; k < ids.size(); ++k) {
@@ -865,7 +902,7 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
     // admission to the first (or only) phase
     {
       std::map<std::tuple<double, int64_t, int64_t>, std::vector<int>> by_params;
-      for (auto& [t, id] : admit(s, *s->eng, s->queue)) {
+      for (auto& [t, id] : admit(s, *s->eng, s->queue, s->admit_nz)) {
         Request& r = s->reqs.at(t);
         const bool polish = s->eng64 && r.tol < s->opt.polish_tol;
         by_params[{polish ? s->opt.polish_tol : r.tol, polish ? fp32_budget(r.max_iter) : r.max_iter,
@@ -878,7 +915,7 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
     }
     // admission to the FP64 polish phase, from the FP32 candidates
     if (s->eng64) {
-      for (auto& [t, id] : admit(s, *s->eng64, s->queue64)) {
+      for (auto& [t, id] : admit(s, *s->eng64, s->queue64, s->admit_nz64)) {
         Request& r = s->reqs.at(t);
         double* buf = s->staging(r.n + r.m_eq + r.m_ineq + 1);
         hip_ok(hipMemcpy(buf, r.px.data(), sizeof(double) * r.n, hipMemcpyHostToDevice), "staging copy");

@@ -49,7 +49,7 @@ struct Options {
   int chunk = 64;
   int use_graph = 1;
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
-  int64_t slice_min_bytes = 2 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
+  int64_t slice_min_bytes = 6 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
   double polish_tol = 1e-3;  // fp32: solve to this tolerance in fp32, then polish in fp64
   // bytes of vectors and matrix tiles the step kernels keep in the last-level
   // (Infinity) cache; tiles beyond it are read with non-temporal loads (< 0: all cached)
@@ -63,7 +63,10 @@ struct Options {
   int slice_rows = kSliceRows;     // rows per sliced row group (<= 256)
   int slice_sort = 1;              // sliced K: column-sorted tiles, LDS-atomic row sums
   int plain_sort = 1;              // unsliced K / K^T: column-sorted blocks, LDS-atomic row sums
-  int sort_rows = kSortRows;       // rows per column-sorted tile (<= kSortRows)
+  int sort_rows = kSortRows;       // most rows per sorted group (plain sorted blocks: at most kSortRowsPlain)
+  int group_threads = 0;           // threads per workgroup of the sorted-group slice kernels: 256, 512, 1024; 0: by size
+  int group_batched = 1;           // 1: a thread's gathers issued together; 0: one gather per LDS add
+  int group_blocks = kMinGroupBlocks;  // fewest workgroups a sorted-group product is cut into
   int restart_mode = 0;            // 0 adaptive, 1 fixed frequency, 2 none
   int64_t fixed_restart_len = 0;   // k* of the fixed-frequency rule
   int verbose = 0;

@@ -262,7 +262,7 @@ static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int in
     ep.r0 = (int32_t)(base + a);
     ep.r1 = (int32_t)(base + std::min<int64_t>(a + kMaxRows, nrows));
     ep.inst = inst;
-    ep.meta = blk_meta(BK_STREAM, kSlices, 0);
+    ep.meta = blk_meta(BK_STREAM, kSlices, 0) | kBlkPart;
     ep.gid = (int32_t)grp.size();
     ep.rp_off = 0;
     ep.p0 = 0;
@@ -302,6 +302,7 @@ struct Slot {
   std::vector<Blk> bP, bD;  // one block per row group (inst field = slot id, gid local)
   std::vector<Blk> bPS, bDS;  // slice blocks of sliced groups (empty when not sliced)
   int64_t brpP0 = 0, brpPn = 0, brpD0 = 0, brpDn = 0;  // ranges in the brp spaces
+  int rowsP = 0, rowsD = 0;  // rows of the largest sorted group of K^T / K (0: not grouped)
   bool watched = false;
   bool reported = false;
 };
@@ -336,8 +337,13 @@ class Engine final : public EngineBase {
   }
 
   int64_t footprint(int64_t n, int64_t m, int64_t nnz) const override {
+    // as allocate() sizes the spaces: per row K_rp, three FP64 and ten (twelve
+    // with sorted blocks) compute-type vectors, the activity byte and the
+    // slice row pointers; per variable the same for K^T's side
     const int64_t s = sizeof(T);
-    const int64_t per_row = 4 + 3 * 8 + 12 * s, per_col = 4 + 5 * 8 + 13 * s;
+    const int64_t brp = opt_.slice_min_bytes >= 0 ? 2 * kSlices * 4 : 0;
+    const int64_t ev = opt_.plain_sort ? 2 * s : 0;
+    const int64_t per_row = 4 + 3 * 8 + 10 * s + ev + 1 + brp, per_col = 4 + 5 * 8 + 11 * s + ev + 1 + brp;
     const int64_t per_nz = 8 + 16 + (sizeof(T) == 8 ? 0 : 2 * s);
     return per_row * (m + 1) + per_col * (n + 1) + per_nz * nnz;
   }
@@ -369,6 +375,10 @@ class Engine final : public EngineBase {
   void rebuild_schedules();
   void pin_to_xcds(std::vector<Blk>& v, const std::vector<std::pair<int, int>>& ranges) const;
   void launch_slices(bool dual, const IterArgs<T>& A, int step);
+  template <bool DUAL>
+  void launch_group(unsigned g, int tpb, size_t lds, const IterArgs<T>& A, int step);
+  int ldsP_ = 0, ldsD_ = 0;  // rows of the largest sorted group in the current schedules
+  int tpbP_ = 256, tpbD_ = 256;  // threads per workgroup of the sorted-group kernels
   void mark_streaming(const std::vector<int>& live, std::vector<Blk>& P, std::vector<Blk>& PS,
                       std::vector<Blk>& DS, std::vector<Blk>& D) const;
   int scheduled_ = 0;          // LPs in the current schedules
@@ -380,7 +390,9 @@ class Engine final : public EngineBase {
   void preprocess(const std::vector<int>& ids, const std::vector<Blk>& nP, const std::vector<Blk>& nD,
                   const std::vector<int4>& nr);
   void slice_matrix(int id, bool dual);
-  void slice_sorted(int id);
+  void group_sorted(int id, bool dual, int nsl, int64_t rows);
+  bool group_shape(int64_t nrows, int64_t width, int nsl_min, int* nsl, int64_t* rows) const;
+  int group_lds_rows(bool dual) const;
   void sort_blocks(int id, bool dual);
   IterArgs<T> args() const;
   void pull_states();
@@ -467,8 +479,10 @@ void Engine<T>::allocate() {
     dalloc(&kt1_, NS_);
     dalloc(&kt2_, NS_);
   }
-  dalloc(&brpK, 2 * kSlices * MS_);
-  dalloc(&brpKT, 2 * kSlices * NS_);
+  // row pointers of row-major slice tiles: only where products may be sliced
+  const bool may_slice = opt_.slice_min_bytes >= 0;
+  dalloc(&brpK, may_slice ? 2 * kSlices * MS_ : 1);
+  dalloc(&brpKT, may_slice ? 2 * kSlices * NS_ : 1);
   dalloc(&d_st, nslots_);
   dalloc(&d_status, nslots_);
   dalloc(&d_cnt, nslots_);
@@ -493,6 +507,16 @@ void Engine<T>::allocate() {
     std::memset(h_status[i], 0, sizeof(int) * nslots_);
   }
   h_st_.resize(nslots_);
+  // sorted groups keep up to kSortRows row sums in dynamic LDS
+  const int lds_max = (int)(sizeof(double) * kSortRows);
+  for (const void* f : {(const void*)sorted_group_step<T, true, 256, true>, (const void*)sorted_group_step<T, true, 256, false>,
+                        (const void*)sorted_group_step<T, true, 512, true>, (const void*)sorted_group_step<T, true, 512, false>,
+                        (const void*)sorted_group_step<T, true, 1024, true>, (const void*)sorted_group_step<T, true, 1024, false>,
+                        (const void*)sorted_group_step<T, false, 256, true>, (const void*)sorted_group_step<T, false, 256, false>,
+                        (const void*)sorted_group_step<T, false, 512, true>, (const void*)sorted_group_step<T, false, 512, false>,
+                        (const void*)sorted_group_step<T, false, 1024, true>,
+                        (const void*)sorted_group_step<T, false, 1024, false>})
+    HIPCHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max));
   HIPCHECK(hipStreamSynchronize(stream_));
 }
 
@@ -917,16 +941,30 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
   }
   compacted_ = false;
   preprocess(ids, nP, nD, nr);
-  // column-slice the matrices whose gathered vector would not stay in one L2
+  // Layout of each product.  A product whose gathered vector would not stay
+  // in one XCD's L2 is column-sliced (8 slices): in sorted groups by default,
+  // in row-major slice tiles with slice_sort = 0.  With sorted layouts on, a
+  // product large enough for sorted groups of more rows than a plain sorted
+  // block holds is stored in sorted groups of 1 or 2 slices (larger groups:
+  // more entries share each cache line of the gathered vector).  The other
+  // products get column-sorted plain blocks (plain_sort) or plain tiles.
   for (int id : ids) {
     const Slot& S = slots_[id];
-    if (opt_.slice_min_bytes >= 0 && S.nnz > 0 && S.n * (int64_t)sizeof(T) > opt_.slice_min_bytes)
-      slice_matrix(id, true);
-    if (opt_.slice_min_bytes >= 0 && S.nnz > 0 && S.m * (int64_t)sizeof(T) > opt_.slice_min_bytes)
-      slice_matrix(id, false);
-    // the other products: column-sorted blocks
-    if (opt_.plain_sort && S.bDS.empty()) sort_blocks(id, true);
-    if (opt_.plain_sort && S.bPS.empty()) sort_blocks(id, false);
+    for (const bool dual : {true, false}) {
+      const int64_t nrows = dual ? S.m : S.n, width = dual ? S.n : S.m;
+      const bool slice = opt_.slice_min_bytes >= 0 && S.nnz > 0 && width * (int64_t)sizeof(T) > opt_.slice_min_bytes;
+      int nsl = 0;
+      int64_t rows = 0;
+      if (slice && !opt_.slice_sort) {
+        slice_matrix(id, dual);
+      } else if (S.nnz > 0 && opt_.slice_sort && (slice || opt_.plain_sort) &&
+                 group_shape(nrows, width, slice ? kSlices : 1, &nsl, &rows) &&
+                 (slice || rows > std::min<int64_t>(opt_.sort_rows, kSortRowsPlain))) {
+        group_sorted(id, dual, nsl, rows);
+      } else if (opt_.plain_sort) {
+        sort_blocks(id, dual);
+      }
+    }
   }
   sched_dirty_ = true;
   for (int id : ids) slots_[id].watched = true;
@@ -1106,10 +1144,6 @@ void Engine<T>::preprocess(const std::vector<int>& ids, const std::vector<Blk>& 
 // (slices over its constraints) into the column-sliced layout.
 template <class T>
 void Engine<T>::slice_matrix(int id, bool dual) {
-  if (dual && opt_.slice_sort) {
-    slice_sorted(id);
-    return;
-  }
   const int NB = opt_.slice_entries;
   Slot& S = slots_[id];
   const int64_t nrows = dual ? S.m : S.n;
@@ -1123,7 +1157,7 @@ void Engine<T>::slice_matrix(int id, bool dual) {
   if (nrows == 0 || S.nnz == 0) return;
   int32_t* d_cnt = nullptr;
   dalloc(&d_cnt, nrows * kSlices);
-  slice_count_kernel<<<nblk(nrows), 256, 0, stream_>>>(rp, ci, r0, nrows, c0, len, d_cnt);
+  slice_count_kernel<<<nblk(nrows), 256, 0, stream_>>>(rp, ci, r0, nrows, c0, len, kSlices, d_cnt);
   std::vector<int32_t> cnt(nrows * kSlices);
   HIPCHECK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, stream_));
   HIPCHECK(hipStreamSynchronize(stream_));
@@ -1306,35 +1340,70 @@ void Engine<T>::sort_blocks(int id, bool dual) {
   else S.bP = out;
 }
 
-// Column-sorted slicing of one LP's K (the dual product's gathers): row
-// groups of at most sort_rows rows and kSortEntries entries per slice; the
-// entries of each (group, slice) block in column order, each column index
-// packed with the entry's row in the group (see blk_rowbits).  Built on the
-// device: keys in row-major block order, a segmented radix sort of the keys
-// within each block (keys are unique in a block, so the order is fixed), and
-// a gather of the values.
+// Shape of a sorted-group layout for a product of nrows rows over `width`
+// columns: the slice count (nsl_min = 8 for a sliced product; else 1 or 2)
+// and the rows per group, the largest that leaves at least group_blocks
+// workgroups per product, fits the packed column index (row bits + column
+// bits of a slice <= 32), Options::sort_rows and kSortRows.  Among the
+// slice counts the one with the larger groups wins (a tie goes to fewer
+// slices: fewer partial sums).  False when no shape fits.
 template <class T>
-void Engine<T>::slice_sorted(int id) {
-  Slot& S = slots_[id];
-  const int64_t nrows = S.m, r0 = S.row0, c0 = S.col0, len = S.n;
-  if (nrows == 0 || S.nnz == 0) return;
-  // bits of a column offset within the widest slice, bits of a row in a group
-  int64_t wmax = 0;
-  for (int q = 0; q < kSlices; ++q) {
-    const int64_t a = (q * len + kSlices - 1) / kSlices, b = ((q + 1) * len + kSlices - 1) / kSlices;
-    wmax = std::max(wmax, b - a);
+bool Engine<T>::group_shape(int64_t nrows, int64_t width, int nsl_min, int* nsl, int64_t* rows) const {
+  int best_s = 0;
+  int64_t best_r = 0;
+  for (int q = nsl_min; q <= (nsl_min == 1 ? 2 : nsl_min); q *= 2) {
+    const int64_t w = (width + q - 1) / q + 1;
+    int cb = 0;
+    while (((int64_t)1 << cb) < w) ++cb;
+    if (cb >= 31) continue;
+    int64_t r = std::min<int64_t>(std::min<int64_t>(opt_.sort_rows, kSortRows), (int64_t)1 << (32 - cb));
+    while (r > kMaxRows && ((nrows + r - 1) / r) * q < opt_.group_blocks) r /= 2;
+    if (r > best_r) {
+      best_r = r;
+      best_s = q;
+    }
   }
-  int cb = 0;
-  while (((int64_t)1 << cb) < wmax) ++cb;
-  int64_t rows = std::min<int64_t>(opt_.sort_rows, kSortRows);
-  if (cb >= 32) throw Error(-1, "LP too wide for sorted slices");
-  rows = std::min<int64_t>(rows, (int64_t)1 << (32 - cb));
+  *nsl = best_s;
+  *rows = best_r;
+  return best_s > 0;
+}
+
+// Rows of the largest sorted group among the live LPs' K (dual) or K^T
+// products: the slice kernel's dynamic LDS holds that many row sums.
+template <class T>
+int Engine<T>::group_lds_rows(bool dual) const {
+  int r = 0;
+  for (const Slot& sl : slots_)
+    if (sl.used) r = std::max(r, dual ? sl.rowsD : sl.rowsP);
+  return r;
+}
+
+// Sorted groups of one LP's K (dual = true; gathers over its variables) or
+// K^T (gathers over its constraints): rows cut into groups of at most `rows`
+// rows and kSortEntries entries per slice, each group's entries into nsl
+// column slices, the entries of each (group, slice) block in column order,
+// each column index packed with the entry's row in the group (see
+// blk_rowbits).  Built on the device: per-slice counts of every row, keys in
+// row-major block order, a segmented radix sort of the keys within each
+// block (keys are unique in a block, so the order is fixed), a gather of the
+// values.
+template <class T>
+void Engine<T>::group_sorted(int id, bool dual, int nsl, int64_t rows) {
+  Slot& S = slots_[id];
+  const int64_t nrows = dual ? S.m : S.n, r0 = dual ? S.row0 : S.col0, c0 = dual ? S.col0 : S.row0;
+  const int64_t len = dual ? S.n : S.m;
+  const int32_t* rp = dual ? K_rp : KT_rp;
+  int32_t* ci = dual ? K_ci : KT_ci;
+  T* val = dual ? K_v : KT_v;
+  double* v64 = dual ? K_v64 : KT_v64;
+  if (nrows == 0 || S.nnz == 0) return;
+  if (nsl < 1 || nsl > kSlices || kSlices % nsl != 0) throw Error(-3, "bad slice count");
   int rb = 0;
   while (((int64_t)1 << rb) < rows) ++rb;
   int32_t* d_cnt = nullptr;
-  dalloc(&d_cnt, nrows * kSlices);
-  slice_count_kernel<<<nblk(nrows), 256, 0, stream_>>>(K_rp, K_ci, r0, nrows, c0, len, d_cnt);
-  std::vector<int32_t> cnt(nrows * kSlices);
+  dalloc(&d_cnt, nrows * nsl);
+  slice_count_kernel<<<nblk(nrows), 256, 0, stream_>>>(rp, ci, r0, nrows, c0, len, nsl, d_cnt);
+  std::vector<int32_t> cnt(nrows * nsl);
   HIPCHECK(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, stream_));
   HIPCHECK(hipStreamSynchronize(stream_));
   dfree(d_cnt);
@@ -1343,62 +1412,64 @@ void Engine<T>::slice_sorted(int id) {
   int64_t start = 0;
   int64_t acc[kSlices] = {0};
   for (int64_t r = 0; r < nrows; ++r) {
-    const int32_t* c = cnt.data() + r * kSlices;
+    const int32_t* c = cnt.data() + r * nsl;
     bool over = (r - start) >= rows;
-    for (int q = 0; q < kSlices; ++q) over |= acc[q] + c[q] > kSortEntries;
+    for (int q = 0; q < nsl; ++q) over |= acc[q] + c[q] > kSortEntries;
     if (over && r > start) {
       groups.emplace_back(start, r);
       start = r;
-      for (int q = 0; q < kSlices; ++q) acc[q] = 0;
+      for (int q = 0; q < nsl; ++q) acc[q] = 0;
     }
-    for (int q = 0; q < kSlices; ++q) acc[q] += c[q];
+    for (int q = 0; q < nsl; ++q) acc[q] += c[q];
   }
   groups.emplace_back(start, nrows);
-  // blocks, row-major positions and the row of each row in its group
+  // step-kernel blocks (kMaxRows rows each, row sums from the partials),
+  // slice blocks, row-major positions and the row of each row in its group
   std::vector<Blk> grp, sl;
   for (int64_t a = 0; a < nrows; a += kMaxRows) {
     Blk ep;
     ep.r0 = (int32_t)(r0 + a);
     ep.r1 = (int32_t)(r0 + std::min<int64_t>(a + kMaxRows, nrows));
     ep.inst = id;
-    ep.meta = blk_meta(BK_STREAM, kSlices, 0);
+    ep.meta = blk_meta(BK_STREAM, nsl, 0) | kBlkPart;
     ep.gid = (int32_t)grp.size();
     ep.rp_off = 0;
     ep.p0 = 0;
     ep.pn = 0;
     grp.push_back(ep);
   }
-  std::vector<int32_t> dst(nrows * kSlices), rloc(nrows), off;
-  int64_t pos = S.nz0;
+  std::vector<int32_t> dst(nrows * nsl), rloc(nrows), off;
+  int64_t pos = S.nz0, maxrows = 0;
   for (size_t g = 0; g < groups.size(); ++g) {
     const int64_t a = groups[g].first, e = groups[g].second;
+    maxrows = std::max(maxrows, e - a);
     for (int64_t r = a; r < e; ++r) rloc[r] = (int32_t)(r - a);
-    for (int q = 0; q < kSlices; ++q) {
+    for (int q = 0; q < nsl; ++q) {
       Blk k;
       k.r0 = (int32_t)(r0 + a);
       k.r1 = (int32_t)(r0 + e);
       k.inst = id;
       k.gid = (int32_t)g;
-      k.rp_off = (int32_t)(c0 + (q * len + kSlices - 1) / kSlices);
+      k.rp_off = (int32_t)(c0 + (q * len + nsl - 1) / nsl);
       k.p0 = (int32_t)pos;
       off.push_back((int32_t)(pos - S.nz0));
       for (int64_t r = a; r < e; ++r) {
-        dst[r * kSlices + q] = (int32_t)pos;
-        pos += cnt[r * kSlices + q];
+        dst[r * nsl + q] = (int32_t)pos;
+        pos += cnt[r * nsl + q];
       }
       k.pn = (int32_t)(pos - k.p0);
-      k.meta = blk_meta(BK_STREAM, kSlices, q) | (rb << 25);
+      k.meta = blk_meta(BK_STREAM, nsl, q) | (rb << 25);
       sl.push_back(k);
     }
   }
   off.push_back((int32_t)(pos - S.nz0));
-  if (pos != S.nz0 + S.nnz) throw Error(-3, "sorted slice layout does not cover the matrix");
+  if (pos != S.nz0 + S.nnz) throw Error(-3, "sorted group layout does not cover the matrix");
   const int64_t nnz = S.nnz;
   int32_t *d_dst = nullptr, *d_rloc = nullptr, *d_off = nullptr, *src_in = nullptr, *src_out = nullptr;
   uint32_t *key_in = nullptr, *key_out = nullptr;
   T* v2 = nullptr;
   double* v642 = nullptr;
-  dalloc(&d_dst, nrows * kSlices);
+  dalloc(&d_dst, nrows * nsl);
   dalloc(&d_rloc, nrows);
   dalloc(&d_off, (int64_t)off.size());
   dalloc(&key_in, nnz);
@@ -1411,7 +1482,7 @@ void Engine<T>::slice_sorted(int id) {
   HIPCHECK(hipMemcpyAsync(d_rloc, rloc.data(), sizeof(int32_t) * rloc.size(), hipMemcpyHostToDevice, stream_));
   HIPCHECK(hipMemcpyAsync(d_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, stream_));
   // positions run from nz0: shift the temporaries by -nz0
-  slice_keys_kernel<<<nblk(nrows), 256, 0, stream_>>>(K_rp, K_ci, r0, nrows, c0, len, d_dst, d_rloc, rb,
+  slice_keys_kernel<<<nblk(nrows), 256, 0, stream_>>>(rp, ci, r0, nrows, c0, len, nsl, d_dst, d_rloc, rb,
                                                       key_in - S.nz0, src_in - S.nz0);
   HIPCHECK(hipGetLastError());
   const int nseg = (int)sl.size();
@@ -1422,11 +1493,10 @@ void Engine<T>::slice_sorted(int id) {
   dalloc(&tmp, (int64_t)tmp_bytes);
   HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, src_in, src_out,
                                                        (int)nnz, nseg, d_off, d_off + 1, 0, 32, stream_));
-  sorted_gather_kernel<T><<<nblk(nnz), 256, 0, stream_>>>(key_out, src_out, K_v, K_v64, nnz, K_ci + S.nz0, v2,
-                                                          v642);
+  sorted_gather_kernel<T><<<nblk(nnz), 256, 0, stream_>>>(key_out, src_out, val, v64, nnz, ci + S.nz0, v2, v642);
   HIPCHECK(hipGetLastError());
-  HIPCHECK(hipMemcpyAsync(K_v + S.nz0, v2, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
-  if (v642) HIPCHECK(hipMemcpyAsync(K_v64 + S.nz0, v642, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
+  HIPCHECK(hipMemcpyAsync(val + S.nz0, v2, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
+  if (v642) HIPCHECK(hipMemcpyAsync(v64 + S.nz0, v642, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
   HIPCHECK(hipStreamSynchronize(stream_));
   dfree(tmp);
   dfree(d_dst);
@@ -1438,11 +1508,21 @@ void Engine<T>::slice_sorted(int id) {
   dfree(src_out);
   dfree(v2);
   dfree(v642);
-  S.bD = grp;
-  S.bDS = sl;
-  S.brpD0 = 0;
-  S.brpDn = 0;
-  if (!spartD) dalloc(&spartD, 3 * kSlices * MS_);
+  if (dual) {
+    S.bD = grp;
+    S.bDS = sl;
+    S.brpD0 = 0;
+    S.brpDn = 0;
+    S.rowsD = (int)maxrows;
+    if (!spartD) dalloc(&spartD, 3 * kSlices * MS_);
+  } else {
+    S.bP = grp;
+    S.bPS = sl;
+    S.brpP0 = 0;
+    S.brpPn = 0;
+    S.rowsP = (int)maxrows;
+    if (!spartP) dalloc(&spartP, 3 * kSlices * NS_);
+  }
 }
 
 template <class T>
@@ -1594,6 +1674,22 @@ void Engine<T>::rebuild_schedules() {
     pin_to_xcds(P, rp);
     pin_to_xcds(D, rd);
   }
+  ldsP_ = ldsD_ = 0;
+  for (int s2 : live) {
+    ldsP_ = std::max(ldsP_, slots_[s2].rowsP);
+    ldsD_ = std::max(ldsD_, slots_[s2].rowsD);
+  }
+  // threads per sorted-group workgroup: the configured count, or enough for
+  // about eight waves per CU over the product's workgroups (measured: the
+  // products are bound by cache-line gathers, so large groups with few
+  // workgroups need wide ones)
+  auto pick = [&](size_t nb) {
+    if (opt_.group_threads > 0) return opt_.group_threads;
+    const int64_t t = (int64_t)kCUs * 8 * 64 / std::max<int64_t>(1, (int64_t)nb);
+    return t >= 1024 ? 1024 : t >= 512 ? 512 : 256;
+  };
+  tpbP_ = pick(PS.size());
+  tpbD_ = pick(DS.size());
   mark_streaming(live, P, PS, DS, D);
   HIPCHECK(hipStreamSynchronize(stream_));
   auto upload = [&](std::vector<Blk>& v, Blk*& d, int64_t& cap, int64_t& n, double** part) {
@@ -1636,11 +1732,36 @@ void Engine<T>::rebuild_schedules() {
   sched_dirty_ = false;
 }
 
+// The sorted-group slice kernel in the configured shape (threads per
+// workgroup, gather order), its dynamic LDS raised to what the groups need.
+template <class T>
+template <bool DUAL>
+void Engine<T>::launch_group(unsigned g, int tpb, size_t lds, const IterArgs<T>& A, int step) {
+  auto go = [&](auto kern, int t) { kern<<<g, t, lds, stream_>>>(A, step); };
+  const bool b = opt_.group_batched != 0;
+  switch (tpb) {
+    case 512:
+      if (b) go(sorted_group_step<T, DUAL, 512, true>, 512);
+      else go(sorted_group_step<T, DUAL, 512, false>, 512);
+      break;
+    case 1024:
+      if (b) go(sorted_group_step<T, DUAL, 1024, true>, 1024);
+      else go(sorted_group_step<T, DUAL, 1024, false>, 1024);
+      break;
+    default:
+      if (b) go(sorted_group_step<T, DUAL, 256, true>, 256);
+      else go(sorted_group_step<T, DUAL, 256, false>, 256);
+      break;
+  }
+}
+
 template <class T>
 void Engine<T>::launch_slices(bool dual, const IterArgs<T>& A, int step) {
   const unsigned g = (unsigned)(dual ? nDS_ : nPS_);
-  if (dual && opt_.slice_sort) {
-    dual_sorted_slice_step<T><<<g, kThreads, 0, stream_>>>(A, step);
+  if (opt_.slice_sort) {
+    const size_t lds = sizeof(double) * (size_t)std::max(1, dual ? ldsD_ : ldsP_);
+    if (dual) launch_group<true>(g, dual ? tpbD_ : tpbP_, lds, A, step);
+    else launch_group<false>(g, dual ? tpbD_ : tpbP_, lds, A, step);
     return;
   }
   switch (opt_.slice_entries) {

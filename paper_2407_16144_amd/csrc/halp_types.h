@@ -55,15 +55,30 @@ __host__ __device__ inline int blk_nsl(const Blk& b) { return (b.meta >> 8) & 0x
 __host__ __device__ inline int blk_slice(const Blk& b) { return (b.meta >> 16) & 0xff; }
 constexpr int32_t kBlkNT = 1 << 24;
 __host__ __device__ inline bool blk_nt(const Blk& b) { return (b.meta & kBlkNT) != 0; }
+// kBlkPart marks a step-kernel block whose row sums are the nsl slice
+// partial sums a slice kernel wrote (sliced or sorted-group products).
+constexpr int32_t kBlkPart = 1 << 30;
+__host__ __device__ inline bool blk_part(const Blk& b) { return (b.meta & kBlkPart) != 0; }
 
-// Column-sorted slice blocks (dual product of a sliced K when
-// Options::slice_sort is on): the block's entries are ordered by column, and
-// each column index is stored as (column - first column of the slice) << rb
-// | (row - b.r0), with rb in meta bits 25..29 and the slice's first column
-// (a space position) in rp_off.  A sorted group has at most kSortRows rows
-// (its row sums sit in LDS) and at most kSortEntries entries per slice.
-constexpr int kSortRows = 4096;
-constexpr int kSortEntries = 1 << 16;
+// Column-sorted row groups (a product stored as "sorted groups": K when its
+// gathered vector is larger than Options::slice_min_bytes, and either
+// product when its matrix is large enough for groups of more rows than a
+// plain sorted block): the rows are cut into groups, each group's entries
+// into nsl column slices (1, 2, 4 or 8; with 8 each slice's gathers stay in
+// one XCD's L2), and the entries of one (group, slice) block are ordered by
+// column, each column index stored as (column - first column of the slice)
+// << rb | (row - b.r0), with rb in meta bits 25..29 and the slice's first
+// column (a space position) in rp_off.  The slice kernel adds a block's
+// products into LDS row sums (at most kSortRows rows per group) and writes
+// them as the group's slice-`slice` partial sums; the step kernel adds the
+// nsl partials of a row in slice order.  A block holds at most kSortEntries
+// entries.
+constexpr int kSortRows = 16384;
+constexpr int kSortEntries = 1 << 18;
+// Sorted-group products are cut into at least this many workgroups (about
+// one per CU); the engine gives each group as many rows as that allows.
+constexpr int kMinGroupBlocks = 240;
+constexpr int kCUs = 256;        // compute units of an MI355X
 // A plain block of the step kernels may be column-sorted too (kind
 // BK_SORTED, same packing, rp_off = the LP's first column): at most
 // kSortRowsPlain rows (its row sums share the step kernel's LDS with the

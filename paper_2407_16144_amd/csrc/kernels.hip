@@ -251,22 +251,28 @@ __device__ __forceinline__ void block_spmv(const Blk& b, const int32_t* __restri
   block_spmv_regs<T, NV, kPlainNB>(b, ci, val, R, s0, s1, s2, s_prod, s_rsum, s_rp, s_red, scale0);
 }
 
-// Row sums of a sliced row group: the kSlices partial sums written by the
-// slice kernel, added in slice order.
+// Row sums of a row group whose products a slice kernel computed: the
+// blk_nsl(b) partial sums per row, added in slice order.
 template <class T, int NV>
 __device__ __forceinline__ void gather_slices(const Blk& b, const T* __restrict__ spart, int64_t space,
                                               T (*s_rsum)[kMaxRows]) {
   const int nrows = b.r1 - b.r0;
+  const int nsl = blk_nsl(b);
   const int t = threadIdx.x;
   if (t < nrows) {
-    // one vector at a time: its kSlices loads in flight together, but not
-    // the NV * kSlices of all vectors (they would set the register budget
-    // of the whole step kernel)
+    // one vector at a time: its partial loads in flight together, but not
+    // the NV * nsl of all vectors (they would set the register budget of the
+    // whole step kernel)
 #pragma unroll 1
     for (int a = 0; a < NV; ++a) {
-      T acc = (T)0;
+      T part[kSlices];
 #pragma unroll
-      for (int q = 0; q < kSlices; ++q) acc += spart[(int64_t)(a * kSlices + q) * space + b.r0 + t];
+      for (int q = 0; q < kSlices; ++q)
+        part[q] = q < nsl ? spart[(int64_t)(a * kSlices + q) * space + b.r0 + t] : (T)0;
+      T acc = part[0];
+#pragma unroll
+      for (int q = 1; q < kSlices; ++q)
+        if (q < nsl) acc += part[q];
       s_rsum[a][t] = acc;
     }
   }
@@ -303,8 +309,10 @@ __device__ __forceinline__ T rec_proj(T d, bool lf, bool uf) {
 // primal step (rows of K^T = variables)
 // ---------------------------------------------------------------------------
 
-// Row sums of one column-sorted block (a sorted slice block, or a plain
-// BK_SORTED block) for the gathered vector src:
+// Row sums of one column-sorted block (a plain BK_SORTED block) for the
+// gathered vector src, accumulated in FP64 LDS words whatever the compute
+// type (products in the compute type; on gfx950 ds_add_f64 measured 1.8x
+// faster than ds_add_f32 on these scattered adds):
 // consecutive entries gather nearby elements of the slice, so the rows of
 // the group share the cache lines of their gathers.  Products go to the LDS
 // row sums s_row by atomic adds, so the order of the additions within a row
@@ -315,7 +323,7 @@ __device__ __forceinline__ T rec_proj(T d, bool lf, bool uf) {
 template <class T, bool NT, int U>
 __device__ __forceinline__ void sorted_rows_sum(const Blk& b, const uint32_t* __restrict__ w,
                                                 const T* __restrict__ val, const T* __restrict__ src,
-                                                T* s_row) {
+                                                double* s_row) {
   const int rb = blk_rowbits(b);
   const uint32_t rmask = (1u << rb) - 1u;
   const T* srcb = src + b.rp_off;
@@ -333,7 +341,7 @@ __device__ __forceinline__ void sorted_rows_sum(const Blk& b, const uint32_t* __
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * kThreads;
-      if (e < b.pn) atomicAdd(&s_row[k[u] & rmask], v[u] * srcb[k[u] >> rb]);
+      if (e < b.pn) atomicAdd(&s_row[k[u] & rmask], (double)(v[u] * srcb[k[u] >> rb]));
     }
   }
 }
@@ -418,9 +426,9 @@ __device__ __forceinline__ void primal_row(const IterArgs<T>& A, const InstState
 // left in s_row[0 .. nrows).
 template <class T>
 __device__ __forceinline__ void sorted_pass(const Blk& b, const int32_t* __restrict__ ci,
-                                            const T* __restrict__ val, const T* __restrict__ src, T* s_row) {
+                                            const T* __restrict__ val, const T* __restrict__ src, double* s_row) {
   const int nrows = b.r1 - b.r0;
-  for (int r = threadIdx.x; r < nrows; r += kThreads) s_row[r] = (T)0;
+  for (int r = threadIdx.x; r < nrows; r += kThreads) s_row[r] = 0.0;
   lds_barrier();
   const uint32_t* w = reinterpret_cast<const uint32_t*>(ci);
   if (blk_nt(b)) sorted_rows_sum<T, true, 4>(b, w, val, src, s_row);
@@ -432,11 +440,11 @@ __device__ __forceinline__ void sorted_pass(const Blk& b, const int32_t* __restr
 // (row r is handled by thread r mod kThreads in every loop over a block).
 template <class T>
 __device__ __forceinline__ void sorted_pass_to(const Blk& b, const int32_t* __restrict__ ci,
-                                               const T* __restrict__ val, const T* __restrict__ src, T* s_row,
+                                               const T* __restrict__ val, const T* __restrict__ src, double* s_row,
                                                T* out) {
   sorted_pass<T>(b, ci, val, src, s_row);
   const int nrows = b.r1 - b.r0;
-  for (int r = threadIdx.x; r < nrows; r += kThreads) out[(int64_t)b.r0 + r] = s_row[r];
+  for (int r = threadIdx.x; r < nrows; r += kThreads) out[(int64_t)b.r0 + r] = (T)s_row[r];
   lds_barrier();
 }
 
@@ -445,7 +453,7 @@ __device__ __forceinline__ void sorted_pass_to(const Blk& b, const int32_t* __re
 // into LDS row sums, then each thread takes the epilogue of every
 // kThreads-th variable.
 template <class T>
-__device__ void primal_sorted(const IterArgs<T>& A, const Blk& b, int step, T* s_row,
+__device__ void primal_sorted(const IterArgs<T>& A, const Blk& b, int step, double* s_row,
                               double (*s_red)[kNS], double* s_out) {
   const InstState& S = A.st[b.inst];
   const int64_t g = *A.gbase + step;
@@ -474,7 +482,7 @@ __device__ void primal_sorted(const IterArgs<T>& A, const Blk& b, int step, T* s
     } else {
       xo = A.x[j];
       x0j = A.x0[j];
-      kty = s_row[r];
+      kty = (T)s_row[r];
       if (mode == M_EVAL) {
         g1 = A.kt1[j];
         g2 = A.kt2[j];
@@ -497,7 +505,7 @@ union StepSmem {
     T rsum[3][kMaxRows];
     int rp[kMaxRows + 1];
   } p;
-  T rows[kSortRowsPlain];
+  double rows[kSortRowsPlain];
 };
 
 template <class T>
@@ -542,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void primal_step(IterArgs<T> A, int step)
     x0j = xo;
     kty = A.ktyp[j];
   }
-  if (blk_nsl(b) > 1) {
+  if (blk_part(b)) {
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartP, A.NS, s_rsum);
     else if (!resid) gather_slices<T, 1>(b, A.spartP, A.NS, s_rsum);
   } else if (mode == M_EVAL) {
@@ -615,31 +623,110 @@ __global__ __launch_bounds__(kThreads) void dual_slice_step(IterArgs<T> A, int s
   slice_body<T, true, NB>(A, step);
 }
 
-// Partial row sums of one column slice of a sorted row group of K (written
-// to spartD for the dual step of the same step to add up), gathering xbar,
-// or xT, cx1 and cx2 one after the other at an eval step.
-template <class T>
-__global__ __launch_bounds__(kThreads) void dual_sorted_slice_step(IterArgs<T> A, int step) {
-  __shared__ T s_row[kSortRows];
-  const Blk b = A.schedDS[blockIdx.x];
+// Row sums of one (group, slice) block of a sorted-group product, TPB
+// threads, U entries in flight per thread.  BATCHED: per batch the U entry
+// loads, then the U gathers, then the U LDS adds, with no branch between
+// them (the gathers of a thread in flight together); otherwise each gather
+// is guarded by its own bounds test (a gather waits for the previous add).
+// Both orders of the additions within a row depend on wave timing.
+template <class T, int TPB, int U, bool BATCHED, bool NT>
+__device__ __forceinline__ void group_rows_sum(const Blk& b, const uint32_t* __restrict__ w,
+                                               const T* __restrict__ val, const T* __restrict__ src,
+                                               double* s_row) {
+  const int rb = blk_rowbits(b);
+  const uint32_t rmask = (1u << rb) - 1u;
+  const T* srcb = src + b.rp_off;
+  const uint32_t* kp = w + b.p0;
+  const T* vp = val + b.p0;
+  const int pn = b.pn;
+  int e0 = threadIdx.x;
+  if constexpr (BATCHED) {
+    const int full = pn - pn % (TPB * U);
+    for (; e0 < full; e0 += TPB * U) {
+      uint32_t k[U];
+      T v[U], g[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        k[u] = ld_entry<NT>(kp + e0 + u * TPB);
+        v[u] = ld_entry<NT>(vp + e0 + u * TPB);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) g[u] = srcb[k[u] >> rb];
+#pragma unroll
+      for (int u = 0; u < U; ++u) atomicAdd(&s_row[k[u] & rmask], (double)(v[u] * g[u]));
+    }
+    if (e0 < pn) {
+      // last partial batch: positions past the block read its first entry
+      // (a valid index) and add nothing
+      uint32_t k[U];
+      T v[U], g[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * TPB;
+        const int ec = e < pn ? e : 0;
+        k[u] = ld_entry<NT>(kp + ec);
+        v[u] = ld_entry<NT>(vp + ec);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) g[u] = srcb[k[u] >> rb];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e0 + u * TPB < pn) atomicAdd(&s_row[k[u] & rmask], (double)(v[u] * g[u]));
+    }
+  } else {
+    for (; e0 < pn; e0 += TPB * U) {
+      uint32_t k[U];
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * TPB;
+        if (e < pn) {
+          k[u] = ld_entry<NT>(kp + e);
+          v[u] = ld_entry<NT>(vp + e);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * TPB;
+        if (e < pn) atomicAdd(&s_row[k[u] & rmask], (double)(v[u] * srcb[k[u] >> rb]));
+      }
+    }
+  }
+}
+
+// Partial row sums of one column slice of a sorted row group (written to the
+// slice-partial buffer for the step kernel of the same step to add up).
+// DUAL: a group of K's rows gathering xbar (xT, cx1 and cx2 one after the
+// other at an eval step) into spartD; otherwise a group of K^T's rows
+// gathering y (yT, cy1, cy2) into spartP.  The group's row sums sit in
+// dynamic LDS (FP64 words for the rows of the largest group of the schedule).
+template <class T, bool DUAL, int TPB, bool BATCHED>
+__global__ __launch_bounds__(TPB) void sorted_group_step(IterArgs<T> A, int step) {
+  extern __shared__ __align__(16) unsigned char group_lds[];
+  double* s_row = reinterpret_cast<double*>(group_lds);
+  const Blk b = (DUAL ? A.schedDS : A.schedPS)[blockIdx.x];
   if (blk_kind(b) == BK_PAD) return;
   const InstState& S = A.st[b.inst];
   const int64_t g = *A.gbase + step;
   const int mode = step_mode(S, g);
-  if (mode == M_SKIP) return;
+  if (mode == M_SKIP || (!DUAL && mode == M_RESID)) return;
   const int nrows = b.r1 - b.r0;
   const int sl = blk_slice(b);
   const int nv = mode == M_EVAL ? 3 : 1;
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(A.K_ci);
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(DUAL ? A.K_ci : A.KT_ci);
+  const T* val = DUAL ? A.K_v : A.KT_v;
+  T* spart = DUAL ? A.spartD : A.spartP;
+  const int64_t space = DUAL ? A.MS : A.NS;
   for (int a = 0; a < nv; ++a) {
-    const T* src = mode != M_EVAL ? A.xbar : a == 0 ? A.xT : a == 1 ? A.cx1 : A.cx2;
-    for (int r = threadIdx.x; r < nrows; r += kThreads) s_row[r] = (T)0;
+    const T* src = DUAL ? (mode != M_EVAL ? A.xbar : a == 0 ? A.xT : a == 1 ? A.cx1 : A.cx2)
+                        : (mode != M_EVAL ? A.y : a == 0 ? A.yT : a == 1 ? A.cy1 : A.cy2);
+    for (int r = threadIdx.x; r < nrows; r += TPB) s_row[r] = 0.0;
     lds_barrier();
-    if (blk_nt(b)) sorted_rows_sum<T, true, 8>(b, w, A.K_v, src, s_row);
-    else sorted_rows_sum<T, false, 8>(b, w, A.K_v, src, s_row);
+    if (blk_nt(b)) group_rows_sum<T, TPB, 4, BATCHED, true>(b, w, val, src, s_row);
+    else group_rows_sum<T, TPB, 4, BATCHED, false>(b, w, val, src, s_row);
     lds_barrier();
-    for (int r = threadIdx.x; r < nrows; r += kThreads)
-      A.spartD[(int64_t)(a * kSlices + sl) * A.MS + b.r0 + r] = s_row[r];
+    for (int r = threadIdx.x; r < nrows; r += TPB)
+      spart[(int64_t)(a * kSlices + sl) * space + b.r0 + r] = (T)s_row[r];
     lds_barrier();
   }
 }
@@ -677,7 +764,8 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
   const int64_t k = (g - 1) - S.kbase;    // inner counter of the check step
   S.tbase += 1;
   S.checks += 1;
-  const double res = sqrt(fmax(S.acc[A_DX2] / S.tau + S.acc[A_DY2] / S.sigma + 2.0 * sd[1], 0.0));
+  const double vres = S.acc[A_DX2] / S.tau + S.acc[A_DY2] / S.sigma + 2.0 * sd[1];
+  const double res = sqrt(fmax(vres, 0.0));
   const double rel_p = sqrt(sd[0]) / (1.0 + S.qnorm);
   const double rel_d = sqrt(sp[0]) / (1.0 + S.cnorm);
   const double pobj = S.acc[A_POBJ];
@@ -695,7 +783,8 @@ __device__ void controller(InstState& S, const double* sp, const double* sd, int
   S.act_changes = (int64_t)(S.acc[A_ACTX] + S.acc[A_ACTY]);
   if (S.act_changes > 0) S.ident_iters = t;
   int st = ST_RUNNING;
-  if (!isfinite(kkt) || !isfinite(res)) {
+  // a NaN or Inf in any reduction (fmax would pass over a NaN part)
+  if (!isfinite(kkt) || !isfinite(vres) || !isfinite(rel_p) || !isfinite(rel_d) || !isfinite(gap)) {
     st = ST_NUMERICAL;
   } else if (kkt <= S.tol) {
     st = ST_OPTIMAL;
@@ -846,7 +935,7 @@ __device__ __forceinline__ void dual_row(const IterArgs<T>& A, const InstState& 
 // constraints): products with xbar (xT, cx1, cx2 at an eval step) added into
 // LDS row sums, then each thread takes the epilogue of every kThreads-th row.
 template <class T>
-__device__ void dual_sorted(const IterArgs<T>& A, const Blk& b, int step, T* s_row, double (*s_red)[kNS],
+__device__ void dual_sorted(const IterArgs<T>& A, const Blk& b, int step, double* s_row, double (*s_red)[kNS],
                             double* s_out) {
   const InstState& S = A.st[b.inst];
   const int64_t g = *A.gbase + step;
@@ -880,7 +969,7 @@ __device__ void dual_sorted(const IterArgs<T>& A, const Blk& b, int step, T* s_r
       a1 = A.kx1[i];
       a2 = A.kx2[i];
     }
-    dual_row<T>(A, S, mode, g, i, qi, yo, y0i, kxpi, s_row[r], a1, a2, ps);
+    dual_row<T>(A, S, mode, g, i, qi, yo, y0i, kxpi, (T)s_row[r], a1, a2, ps);
   }
   if (mode != M_NORMAL) {
     block_sum_ns(ps, s_red, s_out);
@@ -927,7 +1016,7 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
     y0i = yo;
     kxpi = A.kxp[i];
   }
-  if (blk_nsl(b) > 1) {
+  if (blk_part(b)) {
     if (mode == M_EVAL) gather_slices<T, 3>(b, A.spartD, A.MS, s_rsum);
     else gather_slices<T, 1>(b, A.spartD, A.MS, s_rsum);
   } else if (mode == M_EVAL) {
@@ -1307,16 +1396,16 @@ __global__ __launch_bounds__(kThreads) void row_ids_kernel(const Blk* sched, con
 // cnt[(r - r0) * kSlices + s] = entries of row r whose column lies in slice s
 // of the gathered range [c0, c0 + len)
 __global__ void slice_count_kernel(const int32_t* rp, const int32_t* ci, int64_t r0, int64_t nrows,
-                                   int64_t c0, int64_t len, int32_t* cnt) {
+                                   int64_t c0, int64_t len, int nsl, int32_t* cnt) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   int32_t c[kSlices];
   for (int q = 0; q < kSlices; ++q) c[q] = 0;
   for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
-    const int q = (int)(((int64_t)(ci[e] - c0) * kSlices) / len);
+    const int q = (int)(((int64_t)(ci[e] - c0) * nsl) / len);
     c[q] += 1;
   }
-  for (int q = 0; q < kSlices; ++q) cnt[r * kSlices + q] = c[q];
+  for (int q = 0; q < nsl; ++q) cnt[r * nsl + q] = c[q];
 }
 
 // Scatter row r's entries to their slice-major positions: dst[(r - r0) *
@@ -1343,16 +1432,16 @@ __global__ void slice_scatter_kernel(const int32_t* rp, const int32_t* ci, const
 // key (column - first column of its slice) << rb | (r - first row of the
 // group) and the position it came from.
 __global__ void slice_keys_kernel(const int32_t* rp, const int32_t* ci, int64_t r0, int64_t nrows, int64_t c0,
-                                  int64_t len, const int32_t* dst, const int32_t* rloc, int rb,
+                                  int64_t len, int nsl, const int32_t* dst, const int32_t* rloc, int rb,
                                   uint32_t* key_out, int32_t* src_out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   int32_t d[kSlices];
-  for (int q = 0; q < kSlices; ++q) d[q] = dst[r * kSlices + q];
+  for (int q = 0; q < nsl; ++q) d[q] = dst[r * nsl + q];
   for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
     const int64_t c = ci[e] - c0;
-    const int q = (int)((c * kSlices) / len);
-    const int64_t first = (q * len + kSlices - 1) / kSlices;
+    const int q = (int)((c * nsl) / len);
+    const int64_t first = (q * len + nsl - 1) / nsl;
     const int32_t p = d[q]++;
     key_out[p] = ((uint32_t)(c - first) << rb) | (uint32_t)rloc[r];
     src_out[p] = e;
@@ -1540,8 +1629,6 @@ template __global__ void dual_slice_step<double, 1024>(IterArgs<double>, int);
 template __global__ void dual_slice_step<float, 256>(IterArgs<float>, int);
 template __global__ void dual_slice_step<float, 512>(IterArgs<float>, int);
 template __global__ void dual_slice_step<float, 1024>(IterArgs<float>, int);
-template __global__ void dual_sorted_slice_step<double>(IterArgs<double>, int);
-template __global__ void dual_sorted_slice_step<float>(IterArgs<float>, int);
 template __global__ void sorted_block_gather_kernel<double>(const Blk*, int64_t, const uint32_t*,
                                                             const int32_t*, const double*, const double*,
                                                             int32_t*, double*, double*);

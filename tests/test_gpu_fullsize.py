@@ -1,13 +1,26 @@
 """Full-size parity on the large workloads, in the launch configuration the
-benchmark times (column-sliced K, hipGraph chunks of 64 steps).
+benchmark times (default options: column-sorted layouts, K column-sliced,
+hipGraph chunks of 64 steps).
 
 * Single large LP (150k + 50k rows x 1M variables, 9.8M nnz), FP64: the
-  iterates after the first two checks (129+ evaluations of T, one restart)
-  agree with the oracle to 1e-10; a GPU solve to a 1e-3 relative KKT error
-  has that error when the oracle recomputes it from the returned (x, y).
-* Mixed-precision LP (375k + 125k rows x 2M variables, 29.8M nnz), FP32
-  streams: the relative KKT error of the returned point, recomputed by the
-  oracle in FP64, is what the solver reports and within tolerance.
+  iterates after the first check at or past 1000 evaluations of T agree with
+  the oracle's element by element to 1e-10, relative to each entry but with
+  a floor of 1e-2 of the vector's largest entry, with the same iteration and
+  restart counts, every restart decision of the oracle clear of its
+  threshold by more than 1e-8 (so that both sides take the same decisions);
+  a GPU solve to a 1e-3 relative KKT error has that error when the oracle
+  recomputes it.  The floor: the two sides sum in different orders, and an
+  entry far smaller than the terms it is summed from (rows scaled over six
+  decades) carries their rounding, not its own: measured after 1000
+  iterations, the largest difference relative to the vector's largest entry
+  is 8e-13, relative to entries above 1e-2 of it 3e-11, and 2e-8 for entries
+  down to 1e-6 of it, alike with run-to-run (LDS-atomic) and fixed-order sums.
+* Mixed-size LP (375k + 125k rows x 2M variables, 29.6M nnz): FP64 iterates
+  after the first check at or past 320 evaluations (five checks, several
+  restarts) agree with the oracle to 1e-10 in the same sense; an FP32 solve
+  with its FP64 polish phase reaches the 1e-4 relative KKT error when the
+  oracle recomputes it in FP64 from the returned point, and its objective is
+  within the tolerance of the FP64 solve's (both printed).
 """
 import numpy as np
 import pytest
@@ -28,22 +41,39 @@ def large():
     return lpgen.large_single()
 
 
-def _rel(a, b):
-    return float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+@pytest.fixture(scope="module")
+def mixed():
+    return lpgen.large_mixed()
 
 
-@pytest.mark.timeout(400)
-def test_large_trajectory_parity(large):
-    lp = large
-    print("case large trajectory", flush=True)
-    res, x, y, _ = halp.solve_lp(lp, tol=0.0, max_iter=129, on_device=True)
-    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=129))
-    print("gpu", res["iters"], res["restarts"], "oracle", ref.iters, ref.restarts, flush=True)
+def _elementwise(a, b, floor=1e-2):
+    """max_i |a_i - b_i| / max(|b_i|, floor * max|b|)."""
+    f = floor * max(float(np.max(np.abs(b))), 1e-300)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), f)))
+
+
+def _trajectory(lp, iters, name):
+    print(f"case {name} trajectory {iters}", flush=True)
+    res, x, y, _ = halp.solve_lp(lp, tol=0.0, max_iter=iters, on_device=True)
+    ref = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=iters))
+    margins = [e["margin"] for e in ref.log if e["n"] > 0]
+    print("gpu", res["iters"], res["restarts"], "oracle", ref.iters, ref.restarts,
+          "min margin", min(margins) if margins else None, flush=True)
+    assert not margins or min(margins) > 1e-8
     assert res["status"] == halp.LP_ITER_LIMIT == ref.status
     assert res["iters"] == ref.iters and res["restarts"] == ref.restarts
     assert res["sigma_hat"] == pytest.approx(ref.sigma_hat, rel=1e-10)
-    assert _rel(x, ref.x) <= 1e-10
-    assert _rel(y, ref.y) <= 1e-10
+    ex, ey = _elementwise(x, ref.x), _elementwise(y, ref.y)
+    print(f"elementwise relative difference (floor 1e-2) x {ex:.2e} y {ey:.2e}; floor 1e-6: "
+          f"x {_elementwise(x, ref.x, 1e-6):.2e} y {_elementwise(y, ref.y, 1e-6):.2e}", flush=True)
+    assert ex <= 1e-10 and ey <= 1e-10
+    return res, ref
+
+
+@pytest.mark.timeout(600)
+def test_large_trajectory_parity_1000(large):
+    res, ref = _trajectory(large, 1000, "large")
+    assert res["iters"] >= 1000 and res["restarts"] >= 2
 
 
 @pytest.mark.timeout(400)
@@ -58,16 +88,29 @@ def test_large_solution_kkt_property(large):
 
 
 @pytest.mark.timeout(600)
-def test_mixed_precision_large_kkt_property():
-    lp = lpgen.large_mixed()
-    print("case mixed fp32 kkt", flush=True)
+def test_mixed_fp64_trajectory_parity_320(mixed):
+    res, ref = _trajectory(mixed, 320, "mixed fp64")
+    assert res["restarts"] >= 2
+
+
+@pytest.mark.timeout(600)
+def test_mixed_fp32_polish_reaches_tolerance(mixed):
+    lp = mixed
+    tol = 1e-4
+    print("case mixed fp32+polish to 1e-4", flush=True)
     opt = halp.lp_default_options(precision=halp.LP_PREC_FP32)
-    res, x, y, _ = halp.solve_lp(lp, tol=1e-2, max_iter=400_000, opt=opt, on_device=True,
-                                 time_limit=200)
+    res, x, y, _ = halp.solve_lp(lp, tol=tol, max_iter=400_000, opt=opt, on_device=True, time_limit=200)
     assert res["status"] == halp.LP_OPTIMAL, res
-    # the controller sums in FP64 but its products K x+ and K^T y+ are FP32
-    # sums, so the FP64 recomputation may differ slightly from the reported error
+    assert res["polish_iters"] > 0          # the FP64 phase ran
     kkt, parts = oracle.rel_kkt(lp, x, y)
-    print("fp32 reported", res["rel_kkt"], "fp64 recomputed", kkt, parts, flush=True)
-    assert kkt <= 1.5e-2, parts
-    assert abs(kkt - res["rel_kkt"]) <= 2e-3
+    r64, x64, y64, _ = halp.solve_lp(lp, tol=tol, max_iter=400_000, on_device=True, time_limit=200)
+    assert r64["status"] == halp.LP_OPTIMAL, r64
+    kkt64, _ = oracle.rel_kkt(lp, x64, y64)
+    dobj = abs(parts["pobj"] - r64["pobj"]) / (1 + abs(r64["pobj"]))
+    print(f"fp32+polish: iters {res['iters']} (polish {res['polish_iters']}) reported kkt {res['rel_kkt']:.3e} "
+          f"oracle kkt {kkt:.3e} {parts}; fp64: iters {r64['iters']} oracle kkt {kkt64:.3e}; "
+          f"relative objective difference {dobj:.3e}", flush=True)
+    # the polish phase computes its KKT error in FP64 from FP64 products
+    assert kkt <= tol * (1 + 1e-6), parts
+    assert abs(kkt - res["rel_kkt"]) <= 1e-8
+    assert dobj <= tol

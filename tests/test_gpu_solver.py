@@ -39,16 +39,22 @@ def _gpu(lp, tol, max_iter, **kw):
 DET = dict(plain_sort=0, slice_sort=0)
 
 
-def _same_within_tol(lp, tol, ra, xa, ya, rb, xb, yb):
+def _same_within_tol(lp, tol, ra, xa, ya, rb, xb, yb, rays=()):
     """Two solves of one LP that may differ in rounding order: same status;
     optimal results both within tol (KKT error recomputed in FP64 by the
-    oracle) with matching objectives; certificates both valid."""
+    oracle) with matching objectives; the certificates given in `rays`
+    valid by the oracle's Farkas tests."""
     assert ra["status"] == rb["status"], (ra, rb)
     if ra["status"] == halp.LP_OPTIMAL:
         for x, y in ((xa, ya), (xb, yb)):
             kkt, parts = oracle.rel_kkt(lp, x, y)
             assert kkt <= tol * (1 + 1e-6), parts
         assert abs(ra["pobj"] - rb["pobj"]) <= 10 * tol * (1 + abs(ra["pobj"]))
+    for ray in rays:
+        if ra["status"] == halp.LP_PRIMAL_INFEASIBLE:
+            assert oracle.primal_ray_check(lp, ray)[0]
+        elif ra["status"] == halp.LP_DUAL_INFEASIBLE:
+            assert oracle.dual_ray_check(lp, ray)[0]
 
 
 @pytest.mark.parametrize("name,code", METHODS)
@@ -409,6 +415,76 @@ def test_batch_fp32_polish():
     assert oracle.primal_ray_check(lps[-1], out[halp.LP_PREC_FP32][-1][2])[0]
 
 
+def test_fp32_polish_certifies_dual_infeasibility():
+    """A planted-unbounded serving request (an added column with c_j = -1 and
+    positive entries on inequality rows only) solved in FP32 with the FP64
+    polish phase: certified dual infeasible, with a ray that passes the
+    oracle's Farkas test, as the FP64 solve certifies it."""
+    req = [r for r in lpgen.serving_trace(count=400) if r.seed == 240716148170][0]
+    lp = lpgen.request_instance(req)
+    print("case fp32 polish unbounded", flush=True)
+    for prec in (halp.LP_PREC_FP32, halp.LP_PREC_FP64):
+        res, x, y, ray = _gpu(lp, 1e-4, 1_000_000, precision=prec)
+        assert res["status"] == halp.LP_DUAL_INFEASIBLE, (prec, res)
+        ok, info = oracle.dual_ray_check(lp, ray)
+        assert ok, info
+        if prec == halp.LP_PREC_FP32:
+            assert res["polish_iters"] > 0      # certified by the FP64 phase
+
+
+def test_time_limit_status():
+    lp = lpgen.scaled_powerlaw(5, 300, 1000)
+    print("case time limit", flush=True)
+    res, *_ = _gpu(lp, 1e-12, 10_000_000, use_graph=0)
+    assert res["status"] != halp.LP_TIME_LIMIT
+    opt = halp.lp_default_options()
+    r, x, y, _ = halp.solve_lp(lp, tol=1e-12, max_iter=10_000_000, time_limit=0.0, opt=opt)
+    assert r["status"] == halp.LP_TIME_LIMIT, r
+    assert np.all(np.isfinite(x)) and np.all(np.isfinite(y))
+
+
+def test_numerical_status():
+    """An objective whose norm overflows (finite entries of 1e308) makes the
+    initial primal weight infinite, tau = 0 and sigma = inf: the first check
+    sees a non-finite reduction and stops with LP_NUMERICAL, as the oracle
+    does."""
+    lp = lpgen.tiny()
+    c = lp.c.copy()
+    c[:4] = 1e308
+    bad = lpgen.LP(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, c, lp.rhs, lp.lb, lp.ub)
+    print("case numerical", flush=True)
+    res, *_ = _gpu(bad, 1e-6, 100_000)
+    ref = oracle.solve(bad, oracle.Options(tol=1e-6, max_iter=100_000))
+    assert ref.status == core.NUMERICAL
+    assert res["status"] == halp.LP_NUMERICAL, res
+
+
+def test_device_outputs_equal_host_outputs():
+    """lp_get_solution and lp_get_certificate with to_device = 1 write the
+    same values into device memory as into host memory."""
+    for lp, kind in ((lpgen.tiny(), "optimal"), (lpgen.add_contradictory_rows(lpgen.tiny(8), seed=3), "infeasible")):
+        print(f"case device outputs {kind}", flush=True)
+        h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, lp.rowptr, lp.col, lp.val, lp.c, lp.rhs, lp.lb, lp.ub)
+        try:
+            halp.lp_solve(h, 1e-6, 200_000)
+            xh, yh = halp.lp_get_solution(h, lp.n, lp.m)
+            xd = torch.full((lp.n,), float("nan"), dtype=torch.float64, device="cuda")
+            yd = torch.full((lp.m,), float("nan"), dtype=torch.float64, device="cuda")
+            assert halp._lib.lp_get_solution(h, xd.data_ptr(), yd.data_ptr(), 1) == halp.LP_OK
+            assert np.array_equal(xd.cpu().numpy(), xh) and np.array_equal(yd.cpu().numpy(), yh)
+            st = halp.lp_status(h).as_dict()["status"]
+            if kind == "infeasible":
+                assert st == halp.LP_PRIMAL_INFEASIBLE
+                rh = halp.lp_get_certificate(h, lp.m)
+                rd = torch.full((lp.m,), float("nan"), dtype=torch.float64, device="cuda")
+                assert halp._lib.lp_get_certificate(h, rd.data_ptr(), 1) == halp.LP_OK
+                assert np.array_equal(rd.cpu().numpy(), rh)
+            else:
+                assert st == halp.LP_OPTIMAL
+        finally:
+            halp.lp_destroy(h)
+
+
 def test_iteration_limit_and_errors():
     lp = lpgen.tiny()
     print("case limits", flush=True)
@@ -602,11 +678,14 @@ def test_server_results_equal_single_results(prec, graph, det):
         assert not pending
     finally:
         halp.lp_server_destroy(h)
+    # the last two LPs are primal and dual infeasible by construction
+    assert res[len(lps) - 2][0]["status"] == halp.LP_PRIMAL_INFEASIBLE
+    assert res[len(lps) - 1][0]["status"] == halp.LP_DUAL_INFEASIBLE
     for k, lp in enumerate(lps):
-        rs, xs, ys, _ = _gpu(lp, 1e-6, 200_000, use_graph=0, precision=prec, **kw)
+        rs, xs, ys, ray = _gpu(lp, 1e-6, 200_000, use_graph=0, precision=prec, **kw)
         rb, xb, yb = res[k]
         if not det:
-            _same_within_tol(lp, 1e-6, rb, xb, yb, rs, xs, ys)
+            _same_within_tol(lp, 1e-6, rb, xb, yb, rs, xs, ys, rays=[ray] if ray is not None else [])
             continue
         assert rb["status"] == rs["status"] and rb["iters"] == rs["iters"], (k, rb, rs)
         assert rb["polish_iters"] == rs["polish_iters"], k
@@ -640,6 +719,40 @@ def test_server_refuses_lp_larger_than_its_memory():
         assert halp.lp_server_info(h)[0] == 0
     finally:
         halp.lp_server_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [halp.LP_PREC_FP64, halp.LP_PREC_FP32])
+def test_server_stays_within_its_budget(prec):
+    """The device memory a server takes (free memory before and after, while
+    LPs are admitted, solved and polished) stays within hbm_budget_bytes, up
+    to the allocator's rounding."""
+    budget = 300_000_000
+    lps = [lpgen.scaled_powerlaw(500 + i, m, 4 * m) for i, m in enumerate([3000, 1500, 6000, 800, 4000])]
+    print(f"case server budget precision={prec}", flush=True)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    h = halp.lp_server_create(budget, 4, opt=halp.lp_default_options(precision=prec))
+    worst = 0
+    try:
+        tickets = [halp.lp_server_submit(h, lp, 1e-4, 200_000, float(k)) for k, lp in enumerate(lps)]
+        pending = set(tickets)
+        for _ in range(100_000):
+            if not pending:
+                break
+            halp.lp_server_step(h, 2)
+            torch.cuda.synchronize()
+            worst = max(worst, free0 - torch.cuda.mem_get_info()[0])
+            for t in list(pending):
+                r, _ = halp.lp_server_poll(h, t)
+                if r is not None:
+                    assert r.as_dict()["status"] == halp.LP_OPTIMAL
+                    halp.lp_server_release(h, t)
+                    pending.discard(t)
+        assert not pending
+    finally:
+        halp.lp_server_destroy(h)
+    print(f"budget {budget} worst device memory in use {worst}", flush=True)
+    assert worst <= budget + 16 * 2**20
 
 
 def test_mps_model_solves():

@@ -63,9 +63,12 @@ def test_kernel_bytes_split():
     assert sl["primal_slice"] + sl["primal_step"] == p
     assert sl["dual_slice"] + sl["dual_step"] == d
     assert sl["dual_step"] == 4 * s * m and sl["primal_step"] == 7 * s * n
-    # sorted slices of K drop the row pointers of K (packed into the column index)
+    # sorted groups drop the row pointers of both products (packed into the column index)
     so = bench.kernel_bytes(n, m, nnz, s, True, True, True)
     assert so["dual_slice"] == sl["dual_slice"] - 4 * (m + 1)
-    assert so["dual_step"] == sl["dual_step"] and so["primal_slice"] == sl["primal_slice"]
-    # unsliced K: sorting does not apply
+    assert so["primal_slice"] == sl["primal_slice"] - 4 * (n + 1)
+    assert so["dual_step"] == sl["dual_step"] and so["primal_step"] == sl["primal_step"]
+    # products without a slice kernel: sorted groups do not apply; sorted plain blocks do
     assert bench.kernel_bytes(n, m, nnz, s, False, False, True) == plain
+    ps = bench.kernel_bytes(n, m, nnz, s, False, False, False, True)
+    assert ps["primal_step"] == p - 4 * (n + 1) and ps["dual_step"] == d - 4 * (m + 1)
