@@ -402,7 +402,14 @@ def run_serve(args):
                       "solved": solved, "requests": len(trace),
                       "seconds_to_95pct_done": round(sorted(done[i][1] for i in range(len(trace)))[
                           max(0, math.ceil(0.95 * len(trace)) - 1)] - arrivals[0], 2),
-                      "status_by_kind": {k: {str(s): v.count(s) for s in set(v)} for k, v in kinds.items()}}}
+                      "solved_per_s_to_last_solved": round(solved / max(
+                          max((done[i][1] for i in range(len(trace)) if done[i][0]["status"] in (1, 2, 3)),
+                              default=arrivals[0]) - arrivals[0], 1e-9), 3),
+                      "status_by_kind": {k: {str(s): v.count(s) for s in set(v)} for k, v in kinds.items()},
+                      "unfinished": [{"request": i, "kind": trace[i].kind, "seed": trace[i].seed, "m": trace[i].m,
+                                      "n": trace[i].n, "status": done[i][0]["status"], "iters": done[i][0]["iters"],
+                                      "polish_iters": done[i][0]["polish_iters"]}
+                                     for i in range(len(trace)) if done[i][0]["status"] not in (1, 2, 3)]}}
     if args.serial_baseline:
         k = min(args.serial_baseline, len(lps))
         sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)

@@ -104,10 +104,13 @@ typedef struct {
   int use_graph;            /* 1: replay chunks as a captured hipGraph */
   int profile;              /* k > 0: time every k-th chunk's two kernels with HIP
                                events on the solver's stream (see lp_kernel_times) */
-  int64_t slice_min_bytes;  /* store K (K^T) column-sliced, one slice per XCD, when
-                               the vector its product gathers exceeds this many
-                               bytes (default 6 MiB, above the 4 MB L2 of one
-                               XCD; < 0 never) */
+  int64_t slice_min_bytes;  /* column-slice K (K^T) when the vector its product
+                               gathers exceeds this many bytes (default 2 MiB, half
+                               the 4 MB L2 of one XCD; < 0 never): in sorted groups
+                               (slice_sort = 1) into the fewest of 2, 4 or 8 slices
+                               that keep each slice within it, or more where that
+                               allows larger groups; in row-major slice tiles
+                               (slice_sort = 0) into 8, one per XCD */
   double polish_tol;        /* FP32 precision: when the requested tolerance is
                                below this (default 1e-3), solve in FP32 to this
                                tolerance (or to the stall rule, or for at most a
@@ -163,6 +166,12 @@ typedef struct {
   int group_blocks;         /* fewest workgroups a product stored in sorted groups is cut
                                into (default 240, about one per CU): groups get as many
                                rows as that allows */
+  int polish_weight;        /* FP32 precision: the FP64 phase starts from the FP32
+                               candidate with 0 the LP's initial primal weight
+                               ||c~|| / ||q~||, as the method starts; 1 the FP32
+                               phase's last weight; 2 (default) the last weight when
+                               the FP32 phase ended by its stall rule or cap, the
+                               initial one when it reached polish_tol */
 } lp_options;
 
 typedef struct {

@@ -48,7 +48,8 @@ class lp_options(C.Structure):
                 ("restart_mode", C.c_int), ("fixed_restart_len", C.c_int64), ("xcd_pin", C.c_int),
                 ("tile_rows", C.c_int), ("slice_entries", C.c_int), ("slice_rows", C.c_int),
                 ("slice_sort", C.c_int), ("sort_rows", C.c_int), ("plain_sort", C.c_int),
-                ("group_threads", C.c_int), ("group_batched", C.c_int), ("group_blocks", C.c_int)]
+                ("group_threads", C.c_int), ("group_batched", C.c_int), ("group_blocks", C.c_int),
+                ("polish_weight", C.c_int)]
 
 
 class lp_result(C.Structure):

@@ -78,6 +78,7 @@ halp::Options to_opts(const lp_options* o) {
   r.group_threads = o->group_threads;
   r.group_batched = o->group_batched;
   r.group_blocks = o->group_blocks;
+  r.polish_weight = o->polish_weight;
   return r;
 }
 
@@ -95,6 +96,7 @@ void check_opts(const halp::Options& o) {
     throw halp::Error(LP_ERR_INVALID, "group_threads must be 0, 256, 512 or 1024");
   if (o.group_batched < 0 || o.group_batched > 1) throw halp::Error(LP_ERR_INVALID, "group_batched must be 0 or 1");
   if (o.group_blocks < 0) throw halp::Error(LP_ERR_INVALID, "group_blocks must be >= 0");
+  if (o.polish_weight < 0 || o.polish_weight > 2) throw halp::Error(LP_ERR_INVALID, "polish_weight must be 0, 1 or 2");
   if (o.restart_mode == 1 && o.fixed_restart_len < 1)
     throw halp::Error(LP_ERR_INVALID, "fixed restarts need fixed_restart_len >= 1");
   if (o.method < 0 || o.method > 2) throw halp::Error(LP_ERR_INVALID, "method must be 0, 1 or 2");
@@ -271,6 +273,17 @@ struct Polish {
 // converges slowly without stalling still leaves the FP64 phase most of it.
 int64_t fp32_budget(int64_t max_iter) { return std::max<int64_t>(1, max_iter / 10); }
 
+// Primal weight the FP64 phase starts with (import_point: <= 0 means the
+// LP's initial weight): the FP32 phase's last weight when that phase ran
+// until its stall rule or cap (its weight has adapted to the LP), the
+// initial weight when it reached the polish tolerance (often within a few
+// restarts, before its weight settled); polish_weight 0 / 1 force either.
+double polish_omega(const halp::Options& o, const halp::Result& first, double omega) {
+  if (o.polish_weight == 0) return 0.0;
+  if (o.polish_weight == 1) return omega;
+  return first.status == LP_OPTIMAL ? 0.0 : omega;
+}
+
 bool polish_wanted(const halp::Result& r, int64_t max_iter) {
   const bool go = r.status == LP_OPTIMAL || r.status == LP_ITER_LIMIT || r.status == LP_NUMERICAL;
   return go && r.iters < max_iter;
@@ -311,7 +324,7 @@ void run_polish(Polish& P, const halp::Options& opt, hipStream_t stream, halp::E
       const lp_problem& p = raw[i]->view;
       double omega = 1.0;
       src.export_point(src_ids[i], buf, buf + p.n, &omega);
-      P.eng->import_point(ids[k], buf, buf + p.n, omega);
+      P.eng->import_point(ids[k], buf, buf + p.n, polish_omega(opt, P.first[i], omega));
       P.id[i] = ids[k];
       P.eng->set_params({ids[k]}, tol, max_iter - P.first[i].iters);
     }
@@ -415,6 +428,7 @@ void lp_default_options(lp_options* o) {
   o->group_threads = d.group_threads;
   o->group_batched = d.group_batched;
   o->group_blocks = d.group_blocks;
+  o->polish_weight = d.polish_weight;
 }
 
 const char* lp_last_error(void) { return g_err.c_str(); }
@@ -922,7 +936,7 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
         if (!r.py.empty())
           hip_ok(hipMemcpy(buf + r.n, r.py.data(), sizeof(double) * r.py.size(), hipMemcpyHostToDevice),
                  "staging copy");
-        s->eng64->import_point(id, buf, buf + r.n, r.pomega);
+        s->eng64->import_point(id, buf, buf + r.n, polish_omega(s->opt, r.first, r.pomega));
         s->eng64->set_params({id}, r.tol, r.max_iter - r.first.iters);
         r.slot64 = id;
         s->slot_ticket64[id] = t;

@@ -49,8 +49,9 @@ struct Options {
   int chunk = 64;
   int use_graph = 1;
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
-  int64_t slice_min_bytes = 6 << 20;  // column-slice a matrix whose gathered vector is larger (< 0: never)
+  int64_t slice_min_bytes = 2 << 20;  // most bytes of the gathered vector per column slice (< 0: never slice)
   double polish_tol = 1e-3;  // fp32: solve to this tolerance in fp32, then polish in fp64
+  int polish_weight = 2;     // FP64 phase's primal weight: 0 initial, 1 the FP32 phase's last, 2 by how it ended
   // bytes of vectors and matrix tiles the step kernels keep in the last-level
   // (Infinity) cache; tiles beyond it are read with non-temporal loads (< 0: all cached)
   int64_t cache_budget_bytes = 208ll << 20;
@@ -129,7 +130,8 @@ class EngineBase {
   // last check candidate T(z) in the scaled space, as float64 device arrays
   virtual void export_point(int id, double* x, double* y, double* omega) = 0;
   // start the next solve of `id` from (x, y) (scaled, float64 device arrays)
-  // with primal weight omega: iterate and anchor both set to the point
+  // with primal weight omega (omega <= 0: the LP's initial weight
+  // ||c~|| / ||q~||): iterate and anchor both set to the point
   virtual void import_point(int id, const double* x, const double* y, double omega) = 0;
 };
 

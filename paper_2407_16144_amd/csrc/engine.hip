@@ -952,13 +952,18 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
     const Slot& S = slots_[id];
     for (const bool dual : {true, false}) {
       const int64_t nrows = dual ? S.m : S.n, width = dual ? S.n : S.m;
-      const bool slice = opt_.slice_min_bytes >= 0 && S.nnz > 0 && width * (int64_t)sizeof(T) > opt_.slice_min_bytes;
+      // fewest slices that keep each slice of the gathered vector within
+      // slice_min_bytes (1: the product need not be sliced)
+      int nsl_min = 1;
+      if (opt_.slice_min_bytes >= 0 && S.nnz > 0)
+        while (nsl_min < kSlices && width * (int64_t)sizeof(T) > opt_.slice_min_bytes * nsl_min) nsl_min *= 2;
+      const bool slice = nsl_min > 1;
       int nsl = 0;
       int64_t rows = 0;
       if (slice && !opt_.slice_sort) {
         slice_matrix(id, dual);
       } else if (S.nnz > 0 && opt_.slice_sort && (slice || opt_.plain_sort) &&
-                 group_shape(nrows, width, slice ? kSlices : 1, &nsl, &rows) &&
+                 group_shape(nrows, width, nsl_min, &nsl, &rows) &&
                  (slice || rows > std::min<int64_t>(opt_.sort_rows, kSortRowsPlain))) {
         group_sorted(id, dual, nsl, rows);
       } else if (opt_.plain_sort) {
@@ -1341,17 +1346,19 @@ void Engine<T>::sort_blocks(int id, bool dual) {
 }
 
 // Shape of a sorted-group layout for a product of nrows rows over `width`
-// columns: the slice count (nsl_min = 8 for a sliced product; else 1 or 2)
-// and the rows per group, the largest that leaves at least group_blocks
-// workgroups per product, fits the packed column index (row bits + column
-// bits of a slice <= 32), Options::sort_rows and kSortRows.  Among the
-// slice counts the one with the larger groups wins (a tie goes to fewer
+// columns: the slice count, from nsl_min (the fewest that keep a slice of
+// the gathered vector within slice_min_bytes) up to 8 for a product that
+// must be sliced, else 1 or 2, and the rows per group, the largest that
+// leaves at least group_blocks workgroups per product, fits the packed
+// column index (row bits + column bits of a slice <= 32), Options::sort_rows
+// and kSortRows.  More slices allow larger groups of a product with few
+// rows; the slice count with the larger groups wins (a tie goes to fewer
 // slices: fewer partial sums).  False when no shape fits.
 template <class T>
 bool Engine<T>::group_shape(int64_t nrows, int64_t width, int nsl_min, int* nsl, int64_t* rows) const {
   int best_s = 0;
   int64_t best_r = 0;
-  for (int q = nsl_min; q <= (nsl_min == 1 ? 2 : nsl_min); q *= 2) {
+  for (int q = nsl_min; q <= (nsl_min == 1 ? 2 : kSlices); q *= 2) {
     const int64_t w = (width + q - 1) / q + 1;
     int cb = 0;
     while (((int64_t)1 << cb) < w) ++cb;
@@ -2065,9 +2072,11 @@ void Engine<T>::import_point(int id, const double* xi, const double* yi, double 
   InstState st;
   HIPCHECK(hipMemcpyAsync(&st, d_st + id, sizeof(InstState), hipMemcpyDeviceToHost, stream_));
   HIPCHECK(hipStreamSynchronize(stream_));
-  st.omega = omega;
-  st.tau = st.eta / omega;
-  st.sigma = st.eta * omega;
+  if (omega > 0.0 && std::isfinite(omega)) {  // else keep the LP's initial primal weight
+    st.omega = omega;
+    st.tau = st.eta / omega;
+    st.sigma = st.eta * omega;
+  }
   InstState* d_src = nullptr;
   int* d_ids = nullptr;
   dalloc(&d_src, 1);

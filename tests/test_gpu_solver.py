@@ -26,7 +26,12 @@ METHODS = [("rhpdhg", halp.LP_METHOD_RHPDHG), ("r2hpdhg", halp.LP_METHOD_R2HPDHG
 
 
 def _rel(a, b):
-    return float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+    """Element by element: max_i |a_i - b_i| / max(|b_i|, 1e-2 max|b|, 1e-300).
+    The floor keeps entries far below the vector's scale (which carry the
+    rounding of the larger terms they are summed from, in a different order
+    on each side) from deciding the comparison."""
+    f = max(1e-2 * float(np.max(np.abs(b))), 1e-300) if b.size else 1e-300
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), f))) if b.size else 0.0
 
 
 def _gpu(lp, tol, max_iter, **kw):
@@ -382,8 +387,26 @@ def test_fp32_stall_rule_hands_over_to_fp64():
     res, x, y, _ = _gpu(lp, 5e-10, 500_000, precision=halp.LP_PREC_FP32, polish_tol=1e-9, stall_checks=20)
     assert res["status"] == halp.LP_OPTIMAL, res
     assert 0 < res["polish_iters"] < res["iters"] < 250_000, res
+    # the stall rule, not the FP32 phase's cap (a tenth of max_iter), ended the FP32 phase
+    assert res["iters"] - res["polish_iters"] < 50_000 // 2, res
     kkt, parts = oracle.rel_kkt(lp, x, y)
     assert kkt <= 5e-10 * (1 + 1e-6), parts
+
+
+def test_fp32_phase_cap_without_stall_rule():
+    """With the stall rule off, the FP32 phase of a polished solve runs until
+    its cap, a tenth of max_iter (honoured at check granularity), and the
+    FP64 phase gets the rest of the budget."""
+    lp = lpgen.tiny(4)
+    print("case fp32 cap", flush=True)
+    max_iter = 100_000
+    res, x, y, _ = _gpu(lp, 5e-10, max_iter, precision=halp.LP_PREC_FP32, polish_tol=1e-9, stall_checks=0)
+    fp32_iters = res["iters"] - res["polish_iters"]
+    assert max_iter // 10 <= fp32_iters <= max_iter // 10 + 64, res
+    assert res["polish_iters"] > 0 and res["iters"] <= max_iter + 64, res
+    if res["status"] == halp.LP_OPTIMAL:
+        kkt, parts = oracle.rel_kkt(lp, x, y)
+        assert kkt <= 5e-10 * (1 + 1e-6), parts
 
 
 def test_batch_fp32_polish():
