@@ -105,7 +105,7 @@ def test_invalid_options_rejected():
                dict(restart_mode=3), dict(restart_mode=halp.LP_RESTART_FIXED, fixed_restart_len=0),
                dict(tile_rows=0), dict(tile_rows=257), dict(slice_rows=300), dict(slice_entries=700),
                dict(slice_sort=2), dict(sort_rows=0), dict(sort_rows=16385), dict(plain_sort=-1),
-               dict(group_threads=300), dict(group_batched=2), dict(group_blocks=-1), dict(polish_weight=2)]:
+               dict(group_threads=300), dict(group_batched=2), dict(group_blocks=-1), dict(polish_weight=3)]:
         with pytest.raises(halp.HalpError) as ei:
             halp.lp_create(a["n"], a["m_eq"], a["m_ineq"], a["row_ptr"], a["col_idx"], a["val"],
                            a["c"], a["rhs"], a["lb"], a["ub"], opt=halp.lp_default_options(**kw))
