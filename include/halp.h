@@ -166,12 +166,13 @@ typedef struct {
   int group_blocks;         /* fewest workgroups a product stored in sorted groups is cut
                                into (default 240, about one per CU): groups get as many
                                rows as that allows */
-  int polish_weight;        /* FP32 precision: the FP64 phase starts from the FP32
-                               candidate with 0 the LP's initial primal weight
-                               ||c~|| / ||q~||, as the method starts; 1 the FP32
-                               phase's last weight; 2 (default) the last weight when
-                               the FP32 phase ended by its stall rule or cap, the
-                               initial one when it reached polish_tol */
+  int polish_weight;        /* FP32 precision: primal weight of the FP64 phase, which
+                               starts from the FP32 candidate: 1 (default) the FP32
+                               phase's last weight; 0 the LP's initial weight
+                               ||c~|| / ||q~||, as the method starts (fewer
+                               iterations on many LPs, an objective further from the
+                               optimum at the same tolerance); 2 the initial weight
+                               when the FP32 phase reached polish_tol, else the last */
 } lp_options;
 
 typedef struct {

@@ -274,10 +274,14 @@ struct Polish {
 int64_t fp32_budget(int64_t max_iter) { return std::max<int64_t>(1, max_iter / 10); }
 
 // Primal weight the FP64 phase starts with (import_point: <= 0 means the
-// LP's initial weight): the FP32 phase's last weight when that phase ran
-// until its stall rule or cap (its weight has adapted to the LP), the
-// initial weight when it reached the polish tolerance (often within a few
-// restarts, before its weight settled); polish_weight 0 / 1 force either.
+// LP's initial weight ||c~|| / ||q~||).  1 (default): the FP32 phase's last
+// weight, which keeps the balance of primal and dual progress the FP32
+// trajectory found, so the continuation ends near where an FP64 solve would.
+// 0: the initial weight, far larger than the settled one on many LPs: the
+// continuation then mostly corrects the dual side, reaches the tolerance in
+// fewer iterations and keeps much of the FP32 candidate's objective error
+// (the relative KKT error does not bound it).  2: the initial weight when
+// the FP32 phase reached polish_tol, else the last one.
 double polish_omega(const halp::Options& o, const halp::Result& first, double omega) {
   if (o.polish_weight == 0) return 0.0;
   if (o.polish_weight == 1) return omega;

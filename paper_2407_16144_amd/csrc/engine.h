@@ -51,7 +51,7 @@ struct Options {
   int profile = 0;  // > 0: time every profile-th chunk's kernels with HIP events
   int64_t slice_min_bytes = 2 << 20;  // most bytes of the gathered vector per column slice (< 0: never slice)
   double polish_tol = 1e-3;  // fp32: solve to this tolerance in fp32, then polish in fp64
-  int polish_weight = 2;     // FP64 phase's primal weight: 0 initial, 1 the FP32 phase's last, 2 by how it ended
+  int polish_weight = 1;     // FP64 phase's primal weight: 0 initial, 1 the FP32 phase's last, 2 by how it ended
   // bytes of vectors and matrix tiles the step kernels keep in the last-level
   // (Infinity) cache; tiles beyond it are read with non-temporal loads (< 0: all cached)
   int64_t cache_budget_bytes = 208ll << 20;

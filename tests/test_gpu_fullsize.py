@@ -20,7 +20,10 @@ hipGraph chunks of 64 steps).
   restarts) agree with the oracle to 1e-10 in the same sense; an FP32 solve
   with its FP64 polish phase reaches the 1e-4 relative KKT error when the
   oracle recomputes it in FP64 from the returned point, and its objective is
-  within the tolerance of the FP64 solve's (both printed).
+  within the tolerance of the FP64 solve's (both printed).  The relative KKT
+  error does not bound the objective error by itself (on this LP a point
+  whose dual residual is 1.5e-5 of 1 + ||c|| lies 4e-3 from the optimum);
+  the check holds because the FP64 phase carries the FP32 phase's weight.
 """
 import numpy as np
 import pytest
@@ -113,4 +116,5 @@ def test_mixed_fp32_polish_reaches_tolerance(mixed):
     # the polish phase computes its KKT error in FP64 from FP64 products
     assert kkt <= tol * (1 + 1e-6), parts
     assert abs(kkt - res["rel_kkt"]) <= 1e-8
+    # not implied by the tolerance (see above); measured 1.9e-5
     assert dobj <= tol
