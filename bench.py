@@ -239,10 +239,10 @@ def _pct(v, q):
     return v[min(len(v) - 1, max(0, math.ceil(q * len(v)) - 1))]
 
 
-def serial_solve(halp, lps, tol, max_iter):
-    """One LP at a time, FP64 rHPDHG, device-resident inputs: the baseline the
-    batched and serving paths are compared with."""
-    opt = halp.lp_default_options(method=halp.LP_METHOD_RHPDHG)
+def serial_solve(halp, lps, tol, max_iter, method):
+    """One LP at a time, FP64, the same method, device-resident inputs: the
+    baseline the batched and serving paths are compared with."""
+    opt = halp.lp_default_options(method=METHODS[method])
     t0 = time.perf_counter()
     solved = 0
     for i, lp in enumerate(lps):
@@ -333,8 +333,8 @@ def run_batch(args):
            "roofline": roofline}
     if args.serial_baseline:
         k = min(args.serial_baseline, len(lps))
-        sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)
-        out["serial_fp64_rhpdhg"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
+        sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter, args.method)
+        out["serial_fp64"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
                                      "value": round(sv / sw, 3), "unit": "LPs/s"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_pool_baseline(lps, res, args.method)
@@ -412,8 +412,8 @@ def run_serve(args):
                                      for i in range(len(trace)) if done[i][0]["status"] not in (1, 2, 3)]}}
     if args.serial_baseline:
         k = min(args.serial_baseline, len(lps))
-        sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter)
-        out["serial_fp64_rhpdhg"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
+        sv, sw = serial_solve(halp, lps[:k], args.tol, args.max_iter, args.method)
+        out["serial_fp64"] = {"lps": k, "solved": sv, "seconds": round(sw, 2),
                                      "value": round(sv / sw, 3), "unit": "LPs/s"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_pool_baseline(lps, [done[i][0] for i in range(len(trace))], args.method)
