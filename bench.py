@@ -593,6 +593,14 @@ def main():
                    "p50_latency_s": round(p50, 3), "p99_latency_s": round(p99, 3),
                    "rel_kkt": results[-1]["rel_kkt"], "status": halp.STATUS_NAMES[results[-1]["status"]],
                    "power_iters": results[-1]["power_iters"],
+                   # lp_create (validation, transpose, scaling, layouts, power
+                   # iteration) and lp_solve; the four step kernels' event-timed
+                   # time per iteration against the solve's wall time per iteration
+                   "create_s": round(sum(l - r["seconds"] for l, r in zip(lat, results)) / len(lat), 4),
+                   "solve_s": round(sum(r["seconds"] for r in results) / len(results), 4),
+                   "step_kernels_us_per_iter": round(1e3 * tstep, 2),
+                   "solve_us_per_iter": round(1e6 * sum(r["seconds"] for r in results) / max(
+                       1, sum(r["iters"] for r in results)), 2),
                    **({"autotune": tune_info} if tune_info else {})},
         "roofline": roofline,
     }

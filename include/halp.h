@@ -257,6 +257,20 @@ typedef struct {
 /* Fills *out.  LP_ERR_INVALID for a NULL argument. */
 int lp_kernel_times(const lp_solver* s, lp_kernel_timing* out);
 
+/* The constraint matrix as the solver holds it after the preprocessing of
+ * Section 7 (Ruiz and Pock-Chambolle scaling), K~ = D1 K D2 (transpose = 0,
+ * m rows) or the explicit transpose K~^T the solver builds for the K^T y
+ * product (transpose = 1, n rows), as CSR in host arrays supplied by the
+ * caller: row_ptr (rows + 1 entries, from 0), col_idx and val (nnz entries
+ * each, at least 1; column indices from 0, values in FP64).  Entries of a
+ * row are in the order the solver stores them: ascending columns for a
+ * product stored in row order.  Only a product stored in row order can be
+ * read: one kept in column slices or column-sorted blocks or groups (the
+ * default layouts for most LPs; options slice_sort = 0, plain_sort = 0 and
+ * slice_min_bytes = -1 keep row order) gives LP_ERR_STATE.  LP_ERR_INVALID
+ * for a NULL pointer or a transpose other than 0 or 1. */
+int lp_get_scaled_matrix(const lp_solver* s, int transpose, int32_t* row_ptr, int32_t* col_idx, double* val);
+
 void lp_destroy(lp_solver* s);
 
 /* Message of this thread's last error ("" if none). */

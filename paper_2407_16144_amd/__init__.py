@@ -91,6 +91,7 @@ _sig = {
     "lp_get_solution": (C.c_int, [_P, _P, _P, C.c_int]),
     "lp_get_certificate": (C.c_int, [_P, _P, C.c_int]),
     "lp_kernel_times": (C.c_int, [_P, _P]),
+    "lp_get_scaled_matrix": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "lp_destroy": (None, [_P]),
     "lp_batch_create": (C.c_int, [_P, C.c_int, _P, C.c_int, _P, _P]),
     "lp_batch_solve": (C.c_int, [_P, C.c_double, C.c_int64, C.c_double]),
@@ -219,6 +220,16 @@ def lp_kernel_times(h):
     t = lp_kernel_timing()
     _check(_lib.lp_kernel_times(h, C.byref(t)))
     return t.as_dict()
+
+
+def lp_get_scaled_matrix(h, transpose, rows, nnz):
+    """The scaled K (transpose 0, `rows` = m) or K^T (1, `rows` = n) as
+    stored: (row_ptr, col_idx, val) numpy arrays."""
+    rp = np.empty(rows + 1, dtype=np.int32)
+    ci = np.empty(max(nnz, 1), dtype=np.int32)
+    v = np.empty(max(nnz, 1))
+    _check(_lib.lp_get_scaled_matrix(h, int(transpose), rp.ctypes.data, ci.ctypes.data, v.ctypes.data))
+    return rp, ci[:nnz], v[:nnz]
 
 
 def lp_destroy(h):

@@ -527,6 +527,15 @@ int lp_kernel_times(const lp_solver* s, lp_kernel_timing* out) {
   });
 }
 
+int lp_get_scaled_matrix(const lp_solver* s, int transpose, int32_t* row_ptr, int32_t* col_idx, double* val) {
+  return guarded([&]() -> int {
+    if (!s || !row_ptr || !col_idx || !val || (transpose != 0 && transpose != 1))
+      return fail(LP_ERR_INVALID, "bad argument");
+    s->eng->stored_matrix(s->id, transpose != 0, row_ptr, col_idx, val);
+    return LP_OK;
+  });
+}
+
 void lp_destroy(lp_solver* s) {
   try {
     delete s;

@@ -133,6 +133,11 @@ class EngineBase {
   // with primal weight omega (omega <= 0: the LP's initial weight
   // ||c~|| / ||q~||): iterate and anchor both set to the point
   virtual void import_point(int id, const double* x, const double* y, double omega) = 0;
+  // the scaled K (transpose false) or K^T of `id` as stored, CSR with row
+  // pointers from 0 and column indices relative to the LP, FP64 values, into
+  // host arrays; only while that product is stored in row order (no column
+  // slices, no column-sorted blocks or groups), else Error(-4)
+  virtual void stored_matrix(int id, bool transpose, int32_t* rp, int32_t* ci, double* val) = 0;
 };
 
 // Size of the static device workspace of the allocation-free entry point.

@@ -1,7 +1,6 @@
 // Host-side engine of the HIP solver.  This translation unit also holds the
 // kernels (included below), so every launch resolves inside one code object.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -173,6 +172,12 @@ WorkspaceScope::~WorkspaceScope() {
 }
 
 size_t WorkspaceScope::peak() const { return t_ws ? t_ws->peak : 0; }
+
+}  // namespace halp
+
+#include "radix_sort.hip"
+
+namespace halp {
 
 // Workgroup schedule of one LP's rows: consecutive rows are packed into
 // "stream" blocks of at most NB entries and kMaxRows rows; a row with more
@@ -367,6 +372,7 @@ class Engine final : public EngineBase {
   void solution(int id, double* x, double* y, bool to_device) override;
   void certificate(int id, double* ray, bool to_device) override;
   void export_point(int id, double* x, double* y, double* omega) override;
+  void stored_matrix(int id, bool transpose, int32_t* rp, int32_t* ci, double* val) override;
   void import_point(int id, const double* x, const double* y, double omega) override;
 
  private:
@@ -707,34 +713,34 @@ void Engine<T>::transpose_group(int64_t z0, int64_t nnz, int64_t c0, int64_t c1,
                                 const std::vector<Blk>& bD) {
   if (nnz > 0) {
     Blk* d_b = nullptr;
+    int32_t *rowid = nullptr, *vin = nullptr, *vout = nullptr;
+    uint32_t *keys = nullptr, *kout = nullptr;
     dalloc(&d_b, (int64_t)bD.size());
-    int32_t *rowid = nullptr, *keys = nullptr, *vin = nullptr, *vout = nullptr;
     dalloc(&rowid, nnz);
     dalloc(&keys, nnz);
+    dalloc(&kout, nnz);
     dalloc(&vin, nnz);
     dalloc(&vout, nnz);
     HIPCHECK(hipMemcpyAsync(d_b, bD.data(), sizeof(Blk) * bD.size(), hipMemcpyHostToDevice, stream_));
     row_ids_kernel<<<(unsigned)bD.size(), kThreads, 0, stream_>>>(d_b, K_rp, z0, rowid);
     iota_kernel<<<nblk(nnz), 256, 0, stream_>>>(vin, nnz);
-    int end_bit = 1;
-    while (end_bit < 31 && ((int64_t)1 << end_bit) <= c1) ++end_bit;
-    size_t tmp_bytes = 0;
-    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, K_ci + z0, keys, vin, vout, (int)nnz, 0,
-                                                end_bit, stream_));
-    char* tmp = nullptr;
-    dalloc(&tmp, (int64_t)tmp_bytes);
-    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, K_ci + z0, keys, vin, vout, (int)nnz, 0,
-                                                end_bit, stream_));
+    // keys: columns relative to the LP's first column; a stable sort keeps
+    // each column's entries in row order
+    shift_copy_kernel<<<nblk(nnz), 256, 0, stream_>>>((int32_t*)keys, K_ci + z0, nnz, -c0);
+    HIPCHECK(hipGetLastError());
+    std::vector<int> shifts;
+    radix_shifts(shifts, 0, bits_for(c1 - c0));
+    radix_sort_pairs<uint32_t>(keys, vin, kout, vout, nnz, shifts, stream_);
     transpose_gather_kernel<double><<<nblk(nnz), 256, 0, stream_>>>(vout, rowid, K_v64, z0, nnz, KT_ci,
                                                                      KT_v64);
-    transpose_rowptr_kernel<<<nblk(c1 - c0 + 1), 256, 0, stream_>>>(keys, nnz, z0, c0, c1, KT_rp);
+    transpose_rowptr_kernel<<<nblk(c1 - c0 + 1), 256, 0, stream_>>>(kout, nnz, z0, c0, c1, KT_rp);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(stream_));
-    dfree(tmp);
-    dfree(rowid);
-    dfree(keys);
-    dfree(vin);
     dfree(vout);
+    dfree(vin);
+    dfree(kout);
+    dfree(keys);
+    dfree(rowid);
     dfree(d_b);
   } else {
     std::vector<int32_t> h(c1 - c0 + 1, (int32_t)z0);
@@ -1255,7 +1261,6 @@ void Engine<T>::sort_blocks(int id, bool dual) {
   std::vector<int32_t> rp(nrows + 1);
   HIPCHECK(hipMemcpy(rp.data(), rpd + base, sizeof(int32_t) * (nrows + 1), hipMemcpyDeviceToHost));
   std::vector<Blk> out, sorted;
-  std::vector<int32_t> b_off, e_off;
   auto emit = [&](int64_t a, int64_t e, int kind) {
     Blk k;
     k.r0 = (int32_t)(base + a);
@@ -1269,8 +1274,6 @@ void Engine<T>::sort_blocks(int id, bool dual) {
     out.push_back(k);
     if (kind == BK_SORTED) {
       sorted.push_back(k);
-      b_off.push_back((int32_t)(k.p0 - S.nz0));
-      e_off.push_back((int32_t)(k.p0 + k.pn - S.nz0));
     }
   };
   int64_t start = 0, acc = 0;
@@ -1292,37 +1295,39 @@ void Engine<T>::sort_blocks(int id, bool dual) {
   }
   if (nrows > start) emit(start, nrows, BK_SORTED);
   if (!sorted.empty()) {
+    // one stable sort of the LP's entries by (block, key): the entries of
+    // BK_SORTED blocks end in column order, all others where they were
     const int64_t nnz = S.nnz;
     const int nseg = (int)sorted.size();
-    Blk* d_blk = nullptr;
-    int32_t *d_b = nullptr, *d_e = nullptr, *src_in = nullptr, *src_out = nullptr;
-    uint32_t *key_in = nullptr, *key_out = nullptr;
+    const int nall = (int)out.size();
+    Blk *d_all = nullptr, *d_blk = nullptr;
+    int32_t *src_in = nullptr, *src_out = nullptr;
+    uint64_t *key_in = nullptr, *key_out = nullptr;
     T* v_tmp = nullptr;
     double* v64_tmp = nullptr;
+    dalloc(&d_all, nall);
     dalloc(&d_blk, nseg);
-    dalloc(&d_b, nseg);
-    dalloc(&d_e, nseg);
     dalloc(&key_in, nnz);
     dalloc(&key_out, nnz);
     dalloc(&src_in, nnz);
     dalloc(&src_out, nnz);
     dalloc(&v_tmp, nnz);
     if (sizeof(T) != 8) dalloc(&v64_tmp, nnz);
+    HIPCHECK(hipMemcpyAsync(d_all, out.data(), sizeof(Blk) * nall, hipMemcpyHostToDevice, stream_));
     HIPCHECK(hipMemcpyAsync(d_blk, sorted.data(), sizeof(Blk) * nseg, hipMemcpyHostToDevice, stream_));
-    HIPCHECK(hipMemcpyAsync(d_b, b_off.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, stream_));
-    HIPCHECK(hipMemcpyAsync(d_e, e_off.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, stream_));
     HIPCHECK(hipMemcpyAsync(v_tmp, val + S.nz0, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
     if (v64_tmp)
       HIPCHECK(hipMemcpyAsync(v64_tmp, v64 + S.nz0, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
-    sorted_keys_kernel<<<(unsigned)nseg, kThreads, 0, stream_>>>(d_blk, rpd, ci, S.nz0, key_in, src_in);
+    block_keys_kernel<<<(unsigned)nall, kThreads, 0, stream_>>>(d_all, rpd, ci, S.nz0, key_in, src_in);
     HIPCHECK(hipGetLastError());
-    size_t tmp_bytes = 0;
-    HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tmp_bytes, key_in, key_out, src_in, src_out,
-                                                         (int)nnz, nseg, d_b, d_e, 0, 32, stream_));
-    char* tmp = nullptr;
-    dalloc(&tmp, (int64_t)tmp_bytes);
-    HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, src_in, src_out,
-                                                         (int)nnz, nseg, d_b, d_e, 0, 32, stream_));
+    // low word: packed keys below 2^(cb + rb) in sorted blocks, entry
+    // indices below 2^bits_for(longest block) elsewhere
+    int32_t longest = 0;
+    for (const Blk& b : out) longest = std::max(longest, b.pn);
+    std::vector<int> shifts;
+    radix_shifts(shifts, 0, std::min(32, std::max(cb + rb, bits_for(longest))));
+    radix_shifts(shifts, 32, 32 + bits_for(nall - 1));
+    radix_sort_pairs<uint64_t>(key_in, src_in, key_out, src_out, nnz, shifts, stream_);
     sorted_block_gather_kernel<T><<<(unsigned)nseg, kThreads, 0, stream_>>>(d_blk, S.nz0, key_out, src_out, val,
                                                                            v64, ci, v_tmp, v64_tmp);
     HIPCHECK(hipGetLastError());
@@ -1330,16 +1335,14 @@ void Engine<T>::sort_blocks(int id, bool dual) {
     if (v64_tmp)
       HIPCHECK(hipMemcpyAsync(v64 + S.nz0, v64_tmp, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
     HIPCHECK(hipStreamSynchronize(stream_));
-    dfree(tmp);
-    dfree(d_blk);
-    dfree(d_b);
-    dfree(d_e);
-    dfree(key_in);
-    dfree(key_out);
-    dfree(src_in);
-    dfree(src_out);
-    dfree(v_tmp);
     dfree(v64_tmp);
+    dfree(v_tmp);
+    dfree(src_out);
+    dfree(src_in);
+    dfree(key_out);
+    dfree(key_in);
+    dfree(d_blk);
+    dfree(d_all);
   }
   if (dual) S.bD = out;
   else S.bP = out;
@@ -1391,9 +1394,8 @@ int Engine<T>::group_lds_rows(bool dual) const {
 // column slices, the entries of each (group, slice) block in column order,
 // each column index packed with the entry's row in the group (see
 // blk_rowbits).  Built on the device: per-slice counts of every row, keys in
-// row-major block order, a segmented radix sort of the keys within each
-// block (keys are unique in a block, so the order is fixed), a gather of the
-// values.
+// row-major block order, a radix sort by (block, key) (keys are unique in a
+// block, so the order is fixed), a gather of the values.
 template <class T>
 void Engine<T>::group_sorted(int id, bool dual, int nsl, int64_t rows) {
   Slot& S = slots_[id];
@@ -1472,13 +1474,16 @@ void Engine<T>::group_sorted(int id, bool dual, int nsl, int64_t rows) {
   off.push_back((int32_t)(pos - S.nz0));
   if (pos != S.nz0 + S.nnz) throw Error(-3, "sorted group layout does not cover the matrix");
   const int64_t nnz = S.nnz;
+  const int nseg = (int)sl.size();
   int32_t *d_dst = nullptr, *d_rloc = nullptr, *d_off = nullptr, *src_in = nullptr, *src_out = nullptr;
-  uint32_t *key_in = nullptr, *key_out = nullptr;
+  uint32_t* key32 = nullptr;
+  uint64_t *key_in = nullptr, *key_out = nullptr;
   T* v2 = nullptr;
   double* v642 = nullptr;
   dalloc(&d_dst, nrows * nsl);
   dalloc(&d_rloc, nrows);
   dalloc(&d_off, (int64_t)off.size());
+  dalloc(&key32, nnz);
   dalloc(&key_in, nnz);
   dalloc(&key_out, nnz);
   dalloc(&src_in, nnz);
@@ -1490,31 +1495,30 @@ void Engine<T>::group_sorted(int id, bool dual, int nsl, int64_t rows) {
   HIPCHECK(hipMemcpyAsync(d_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, stream_));
   // positions run from nz0: shift the temporaries by -nz0
   slice_keys_kernel<<<nblk(nrows), 256, 0, stream_>>>(rp, ci, r0, nrows, c0, len, nsl, d_dst, d_rloc, rb,
-                                                      key_in - S.nz0, src_in - S.nz0);
+                                                      key32 - S.nz0, src_in - S.nz0);
+  segment_keys_kernel<<<(unsigned)nseg, kThreads, 0, stream_>>>(d_off, key32, key_in);
   HIPCHECK(hipGetLastError());
-  const int nseg = (int)sl.size();
-  size_t tmp_bytes = 0;
-  HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tmp_bytes, key_in, key_out, src_in, src_out,
-                                                       (int)nnz, nseg, d_off, d_off + 1, 0, 32, stream_));
-  char* tmp = nullptr;
-  dalloc(&tmp, (int64_t)tmp_bytes);
-  HIPCHECK(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, key_in, key_out, src_in, src_out,
-                                                       (int)nnz, nseg, d_off, d_off + 1, 0, 32, stream_));
+  // one stable sort by (block, packed key): keys are unique within a block,
+  // so each block ends in column order
+  std::vector<int> shifts;
+  radix_shifts(shifts, 0, std::min(32, bits_for((len + nsl - 1) / nsl) + rb));
+  radix_shifts(shifts, 32, 32 + bits_for(nseg - 1));
+  radix_sort_pairs<uint64_t>(key_in, src_in, key_out, src_out, nnz, shifts, stream_);
   sorted_gather_kernel<T><<<nblk(nnz), 256, 0, stream_>>>(key_out, src_out, val, v64, nnz, ci + S.nz0, v2, v642);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipMemcpyAsync(val + S.nz0, v2, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
   if (v642) HIPCHECK(hipMemcpyAsync(v64 + S.nz0, v642, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
   HIPCHECK(hipStreamSynchronize(stream_));
-  dfree(tmp);
-  dfree(d_dst);
-  dfree(d_rloc);
-  dfree(d_off);
-  dfree(key_in);
-  dfree(key_out);
-  dfree(src_in);
-  dfree(src_out);
-  dfree(v2);
   dfree(v642);
+  dfree(v2);
+  dfree(src_out);
+  dfree(src_in);
+  dfree(key_out);
+  dfree(key_in);
+  dfree(key32);
+  dfree(d_off);
+  dfree(d_rloc);
+  dfree(d_dst);
   if (dual) {
     S.bD = grp;
     S.bDS = sl;
@@ -2088,6 +2092,28 @@ void Engine<T>::import_point(int id, const double* xi, const double* yi, double 
   HIPCHECK(hipStreamSynchronize(stream_));
   dfree(d_src);
   dfree(d_ids);
+}
+
+template <class T>
+void Engine<T>::stored_matrix(int id, bool transpose, int32_t* rp, int32_t* ci, double* val) {
+  if (id < 0 || id >= nslots_ || !slots_[id].used) throw Error(-1, "invalid LP id");
+  const Slot& S = slots_[id];
+  const std::vector<Blk>& blocks = transpose ? S.bP : S.bD;
+  const std::vector<Blk>& slices = transpose ? S.bPS : S.bDS;
+  bool row_order = slices.empty();
+  for (const Blk& b : blocks) row_order &= blk_kind(b) != BK_SORTED && !blk_part(b);
+  if (!row_order) throw Error(-4, "the product is not stored in row order (column slices or sorted layout)");
+  const int64_t rows = transpose ? S.n : S.m, r0 = transpose ? S.col0 : S.row0;
+  const int64_t c0 = transpose ? S.row0 : S.col0;
+  HIPCHECK(hipStreamSynchronize(stream_));
+  HIPCHECK(hipMemcpy(rp, (transpose ? KT_rp : K_rp) + r0, sizeof(int32_t) * (rows + 1), hipMemcpyDeviceToHost));
+  if (S.nnz > 0) {
+    HIPCHECK(hipMemcpy(ci, (transpose ? KT_ci : K_ci) + S.nz0, sizeof(int32_t) * S.nnz, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(val, (transpose ? KT_v64 : K_v64) + S.nz0, sizeof(double) * S.nnz,
+                       hipMemcpyDeviceToHost));
+  }
+  for (int64_t r = 0; r <= rows; ++r) rp[r] -= (int32_t)S.nz0;
+  for (int64_t e = 0; e < S.nnz; ++e) ci[e] -= (int32_t)c0;
 }
 
 std::unique_ptr<EngineBase> make_engine(const Options& opt, hipStream_t stream, int64_t cap_m, int64_t cap_n,

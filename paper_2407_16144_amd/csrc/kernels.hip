@@ -1448,29 +1448,42 @@ __global__ void slice_keys_kernel(const int32_t* rp, const int32_t* ci, int64_t 
   }
 }
 
-// Column-sorting of plain blocks (BK_SORTED), step 1: for every entry of
-// the block, its sort key (column - b.rp_off) << rb | (row - b.r0) and its
-// position.  Positions are relative to nz0 in the key arrays.
-__global__ __launch_bounds__(kThreads) void sorted_keys_kernel(const Blk* blks, const int32_t* rp,
-                                                               const int32_t* ci, int64_t nz0, uint32_t* key,
-                                                               int32_t* src) {
+// Column-sorting of plain blocks, step 1: for every entry of every block of
+// one LP's schedule (blocks in position order, covering its entries), a
+// 64-bit sort key with the block's index in the high word and, in the low
+// word, (column - b.rp_off) << rb | (row - b.r0) for a BK_SORTED block, the
+// entry's index in the block for any other (so that it stays in place), and
+// the entry's position.  Positions are relative to nz0 in the key arrays.
+__global__ __launch_bounds__(kThreads) void block_keys_kernel(const Blk* blks, const int32_t* rp,
+                                                              const int32_t* ci, int64_t nz0, uint64_t* key,
+                                                              int32_t* src) {
   const Blk b = blks[blockIdx.x];
-  const int rb = blk_rowbits(b);
-  const int nrows = b.r1 - b.r0;
-  for (int r = threadIdx.x; r < nrows; r += kThreads) {
-    for (int32_t e = rp[b.r0 + r]; e < rp[b.r0 + r + 1]; ++e) {
-      key[e - nz0] = ((uint32_t)(ci[e] - b.rp_off) << rb) | (uint32_t)r;
-      src[e - nz0] = e;
+  const uint64_t hi = (uint64_t)blockIdx.x << 32;
+  if (blk_kind(b) == BK_SORTED) {
+    const int rb = blk_rowbits(b);
+    const int nrows = b.r1 - b.r0;
+    for (int r = threadIdx.x; r < nrows; r += kThreads) {
+      for (int32_t e = rp[b.r0 + r]; e < rp[b.r0 + r + 1]; ++e) {
+        key[e - nz0] = hi | (((uint32_t)(ci[e] - b.rp_off) << rb) | (uint32_t)r);
+        src[e - nz0] = e;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < b.pn; e += kThreads) {
+      const int64_t p = (int64_t)b.p0 + e;
+      key[p - nz0] = hi | (uint32_t)e;
+      src[p - nz0] = (int32_t)p;
     }
   }
 }
 
-// Step 2 (after the keys are sorted within each block): the block's entries
-// take the sorted keys as packed column indices and the values of the
-// entries they came from (values staged in v_tmp / v64_tmp, relative to nz0).
+// Step 2 (after the keys are sorted): the entries of every BK_SORTED block
+// take the low words of the sorted keys as packed column indices and the
+// values of the entries they came from (values staged in v_tmp / v64_tmp,
+// relative to nz0).
 template <class V>
 __global__ __launch_bounds__(kThreads) void sorted_block_gather_kernel(const Blk* blks, int64_t nz0,
-                                                                       const uint32_t* key, const int32_t* src,
+                                                                       const uint64_t* key, const int32_t* src,
                                                                        const V* val, const double* v64,
                                                                        int32_t* ci_out, V* v_tmp,
                                                                        double* v64_tmp) {
@@ -1479,22 +1492,31 @@ __global__ __launch_bounds__(kThreads) void sorted_block_gather_kernel(const Blk
     const int64_t p = (int64_t)b.p0 + e;
     const int64_t rel = p - nz0;
     const int32_t from = src[rel];
-    ci_out[p] = (int32_t)key[rel];
+    ci_out[p] = (int32_t)(uint32_t)key[rel];
     v_tmp[rel] = val[from];
     if (v64_tmp) v64_tmp[rel] = v64[from];
   }
+}
+
+// Sorted groups: the key of every entry gets its (group, slice) block's
+// index in the high word; block s holds positions [off[s], off[s + 1]).
+__global__ __launch_bounds__(kThreads) void segment_keys_kernel(const int32_t* off, const uint32_t* k32,
+                                                                uint64_t* k64) {
+  const int s = blockIdx.x;
+  const uint64_t hi = (uint64_t)s << 32;
+  for (int64_t p = off[s] + threadIdx.x; p < off[s + 1]; p += kThreads) k64[p] = hi | k32[p];
 }
 
 // Sorted slicing, step 2 (after the keys are sorted within each block):
 // entry p takes the sorted key as its packed column index and the value of
 // the entry it came from.
 template <class V>
-__global__ void sorted_gather_kernel(const uint32_t* key, const int32_t* src, const V* val, const double* v64,
+__global__ void sorted_gather_kernel(const uint64_t* key, const int32_t* src, const V* val, const double* v64,
                                      int64_t nnz, int32_t* ci_out, V* val_out, double* v64_out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nnz) return;
   const int32_t e = src[p];
-  ci_out[p] = (int32_t)key[p];
+  ci_out[p] = (int32_t)(uint32_t)key[p];
   val_out[p] = val[e];
   if (v64_out) v64_out[p] = v64[e];
 }
@@ -1509,15 +1531,16 @@ __global__ void transpose_gather_kernel(const int32_t* perm, const int32_t* rowi
   kt_val[z0 + p] = val[z0 + e];
 }
 
-// kt_rp[j] = z0 + #{sorted keys < j} for space positions j in [c0, c1]
-__global__ void transpose_rowptr_kernel(const int32_t* keys, int64_t nnz, int64_t z0, int64_t c0,
+// kt_rp[j] = z0 + #{sorted keys < j - c0} for space positions j in [c0, c1]
+// (keys: columns relative to c0)
+__global__ void transpose_rowptr_kernel(const uint32_t* keys, int64_t nnz, int64_t z0, int64_t c0,
                                         int64_t c1, int32_t* kt_rp) {
   const int64_t j = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j > c1) return;
   int64_t lo = 0, hi = nnz;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)keys[mid] < j) lo = mid + 1; else hi = mid;
+    if ((int64_t)keys[mid] + c0 < j) lo = mid + 1; else hi = mid;
   }
   kt_rp[j] = (int32_t)(z0 + lo);
 }
@@ -1629,15 +1652,15 @@ template __global__ void dual_slice_step<double, 1024>(IterArgs<double>, int);
 template __global__ void dual_slice_step<float, 256>(IterArgs<float>, int);
 template __global__ void dual_slice_step<float, 512>(IterArgs<float>, int);
 template __global__ void dual_slice_step<float, 1024>(IterArgs<float>, int);
-template __global__ void sorted_block_gather_kernel<double>(const Blk*, int64_t, const uint32_t*,
+template __global__ void sorted_block_gather_kernel<double>(const Blk*, int64_t, const uint64_t*,
                                                             const int32_t*, const double*, const double*,
                                                             int32_t*, double*, double*);
-template __global__ void sorted_block_gather_kernel<float>(const Blk*, int64_t, const uint32_t*,
+template __global__ void sorted_block_gather_kernel<float>(const Blk*, int64_t, const uint64_t*,
                                                            const int32_t*, const float*, const double*,
                                                            int32_t*, float*, double*);
-template __global__ void sorted_gather_kernel<double>(const uint32_t*, const int32_t*, const double*,
+template __global__ void sorted_gather_kernel<double>(const uint64_t*, const int32_t*, const double*,
                                                       const double*, int64_t, int32_t*, double*, double*);
-template __global__ void sorted_gather_kernel<float>(const uint32_t*, const int32_t*, const float*,
+template __global__ void sorted_gather_kernel<float>(const uint64_t*, const int32_t*, const float*,
                                                      const double*, int64_t, int32_t*, float*, double*);
 template __global__ void cast_kernel<float>(const double*, float*, int64_t);
 template __global__ void scale_primal_kernel<double>(const Blk*, const double*, const double*,
