@@ -14,6 +14,7 @@
 
 #include "engine.h"
 #include "kernels.hip"
+#include "layout_kernels.hip"
 
 namespace halp {
 
@@ -300,6 +301,20 @@ static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int in
   }
 }
 
+// Blocks per product of a column-sorted LP: at least kMinSortedBlocks (rows
+// down to kMaxRows) in engines of many LPs, whose products share each
+// launch; at least kMinSortedBlocksAlone (rows down to kMinSortedRows) for an
+// LP that runs alone, where the product's blocks are all the launch has
+// (measured on MI355X, LPs of 12.8k and 18.6k rows alone: 21.4 and 36.8 us
+// per iteration with 256-row blocks, 13.0 and 17.5 us with 128-row blocks;
+// in a batch of 512 such LPs 64-row blocks everywhere cost 7% over the
+// default).  A batch re-blocks its remaining LPs when few are left.
+constexpr int64_t kMinSortedBlocks = 64;
+constexpr int64_t kMinSortedBlocksAlone = 192;
+constexpr int64_t kMinSortedRows = 64;
+// a batch's products keep at least this many workgroups as LPs finish
+constexpr int64_t kTailBlocks = 768;
+
 struct Slot {
   bool used = false;
   int64_t n = 0, m = 0, m_eq = 0, nnz = 0;
@@ -308,6 +323,7 @@ struct Slot {
   std::vector<Blk> bPS, bDS;  // slice blocks of sliced groups (empty when not sliced)
   int64_t brpP0 = 0, brpPn = 0, brpD0 = 0, brpDn = 0;  // ranges in the brp spaces
   int rowsP = 0, rowsD = 0;  // rows of the largest sorted group of K^T / K (0: not grouped)
+  int64_t plainP = 0, plainD = 0;  // row cap of K^T's / K's column-sorted plain blocks (0: none)
   bool watched = false;
   bool reported = false;
 };
@@ -399,7 +415,9 @@ class Engine final : public EngineBase {
   void group_sorted(int id, bool dual, int nsl, int64_t rows);
   bool group_shape(int64_t nrows, int64_t width, int nsl_min, int* nsl, int64_t* rows) const;
   int group_lds_rows(bool dual) const;
-  void sort_blocks(int id, bool dual);
+  void sort_blocks(int id, bool dual, int64_t min_blocks, int64_t min_rows, bool reblock);
+  void reblock_for(const int* status);
+  int64_t plain_rows(int64_t nrows, int64_t width, int64_t min_blocks, int64_t min_rows) const;
   IterArgs<T> args() const;
   void pull_states();
 
@@ -973,7 +991,8 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
                  (slice || rows > std::min<int64_t>(opt_.sort_rows, kSortRowsPlain))) {
         group_sorted(id, dual, nsl, rows);
       } else if (opt_.plain_sort) {
-        sort_blocks(id, dual);
+        sort_blocks(id, dual, nslots_ == 1 ? kMinSortedBlocksAlone : kMinSortedBlocks,
+                    nslots_ == 1 ? kMinSortedRows : kMaxRows, false);
       }
     }
   }
@@ -1226,17 +1245,55 @@ void Engine<T>::slice_matrix(int id, bool dual) {
   if (!dual && !spartP) dalloc(&spartP, 3 * kSlices * NS_);
 }
 
-constexpr int64_t kMinSortedBlocks = 64;
+
+// Row cap of the column-sorted plain blocks of a product of nrows rows over
+// `width` columns (the packed index holds the column and the row in the
+// block in 32 bits).
+template <class T>
+int64_t Engine<T>::plain_rows(int64_t nrows, int64_t width, int64_t min_blocks, int64_t min_rows) const {
+  int cb = 0;
+  while (((int64_t)1 << cb) < width) ++cb;
+  const int64_t rows =
+      std::min<int64_t>(std::min<int64_t>(opt_.sort_rows, kSortRowsPlain), (int64_t)1 << (32 - std::min(cb, 31)));
+  return std::min<int64_t>(rows, std::max<int64_t>(min_rows, (nrows + min_blocks - 1) / min_blocks));
+}
+
+// Smaller column-sorted blocks for the LPs still running (status) when few
+// are left: each gets at least kTailBlocks / (running LPs) blocks per
+// product, down to kMinSortedRows rows, so that the launches keep the CUs
+// busy.  Products in sorted groups, column slices or plain tiles keep their
+// layout.
+template <class T>
+void Engine<T>::reblock_for(const int* status) {
+  std::vector<int> run;
+  for (int s = 0; s < nslots_; ++s)
+    if (slots_[s].used && status[s] == ST_RUNNING) run.push_back(s);
+  if (run.empty()) return;
+  const int64_t minb = (kTailBlocks + (int64_t)run.size() - 1) / (int64_t)run.size();
+  for (int s : run) {
+    for (int d = 0; d < 2; ++d) {
+      const bool dual = d == 1;
+      const Slot& S = slots_[s];
+      const int64_t cur = dual ? S.plainD : S.plainP;
+      if (cur == 0) continue;
+      if (plain_rows(dual ? S.m : S.n, dual ? S.n : S.m, minb, kMinSortedRows) < cur)
+        sort_blocks(s, dual, minb, kMinSortedRows, true);
+    }
+  }
+}
 
 // Column-sorted blocks of one LP's K (dual = true) or K^T, for a product
 // that is not column-sliced: rows longer than a plain tile keep a long
 // block; the other rows go to blocks of at most min(sort_rows,
-// kSortRowsPlain, max(kMaxRows, rows / kMinSortedBlocks)) rows and
-// kSortEntries entries whose entries are put in
-// column order (keys sorted within each block on the device), each column
-// index packed with the entry's row in the block (see blk_rowbits).
+// kSortRowsPlain, max(min_rows, rows / min_blocks)) rows and kSortEntries
+// entries whose entries are put in column order, each column index packed
+// with the entry's row in the block (see blk_rowbits).  Built on the device:
+// a 64-bit key per entry (block index, packed key) and one stable radix
+// sort.  From the row-major input (reblock false), or re-blocking a product
+// already in column-sorted blocks into smaller ones (reblock true: each
+// entry's row and column are read back from its packed key).
 template <class T>
-void Engine<T>::sort_blocks(int id, bool dual) {
+void Engine<T>::sort_blocks(int id, bool dual, int64_t min_blocks, int64_t min_rows, bool reblock) {
   Slot& S = slots_[id];
   const int64_t nrows = dual ? S.m : S.n;
   const int64_t base = dual ? S.row0 : S.col0;
@@ -1250,12 +1307,7 @@ void Engine<T>::sort_blocks(int id, bool dual) {
   int cb = 0;
   while (((int64_t)1 << cb) < width) ++cb;
   if (cb >= 32) return;
-  int64_t rows = std::min<int64_t>(std::min<int64_t>(opt_.sort_rows, kSortRowsPlain), (int64_t)1 << (32 - cb));
-  // at least kMinSortedBlocks blocks per product where rows allow (down to
-  // kMaxRows-row blocks): an LP that runs alone at the end of a batch then
-  // still spreads over many workgroups, and a small LP's gathered vector is
-  // small enough that short blocks keep most of the cache-line sharing
-  rows = std::min<int64_t>(rows, std::max<int64_t>(kMaxRows, (nrows + kMinSortedBlocks - 1) / kMinSortedBlocks));
+  const int64_t rows = plain_rows(nrows, width, min_blocks, min_rows);
   int rb = 0;
   while (((int64_t)1 << rb) < rows) ++rb;
   std::vector<int32_t> rp(nrows + 1);
@@ -1318,7 +1370,24 @@ void Engine<T>::sort_blocks(int id, bool dual) {
     HIPCHECK(hipMemcpyAsync(v_tmp, val + S.nz0, sizeof(T) * nnz, hipMemcpyDeviceToDevice, stream_));
     if (v64_tmp)
       HIPCHECK(hipMemcpyAsync(v64_tmp, v64 + S.nz0, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
-    block_keys_kernel<<<(unsigned)nall, kThreads, 0, stream_>>>(d_all, rpd, ci, S.nz0, key_in, src_in);
+    Blk* d_old = nullptr;
+    int2* d_where = nullptr;
+    if (!reblock) {
+      block_keys_kernel<<<(unsigned)nall, kThreads, 0, stream_>>>(d_all, rpd, ci, S.nz0, key_in, src_in);
+    } else {
+      // each row's new block and its row in that block
+      const std::vector<Blk>& old_blocks = dual ? S.bD : S.bP;
+      std::vector<int2> where(nrows);
+      for (int bi = 0; bi < nall; ++bi)
+        for (int32_t r = out[bi].r0; r < out[bi].r1; ++r) where[r - base] = make_int2(bi, r - out[bi].r0);
+      dalloc(&d_old, (int64_t)old_blocks.size());
+      dalloc(&d_where, nrows);
+      HIPCHECK(hipMemcpyAsync(d_old, old_blocks.data(), sizeof(Blk) * old_blocks.size(), hipMemcpyHostToDevice,
+                              stream_));
+      HIPCHECK(hipMemcpyAsync(d_where, where.data(), sizeof(int2) * nrows, hipMemcpyHostToDevice, stream_));
+      reblock_keys_kernel<<<(unsigned)old_blocks.size(), kThreads, 0, stream_>>>(d_old, d_where, base, rb, ci,
+                                                                                   S.nz0, key_in, src_in);
+    }
     HIPCHECK(hipGetLastError());
     // low word: packed keys below 2^(cb + rb) in sorted blocks, entry
     // indices below 2^bits_for(longest block) elsewhere
@@ -1335,6 +1404,8 @@ void Engine<T>::sort_blocks(int id, bool dual) {
     if (v64_tmp)
       HIPCHECK(hipMemcpyAsync(v64 + S.nz0, v64_tmp, sizeof(double) * nnz, hipMemcpyDeviceToDevice, stream_));
     HIPCHECK(hipStreamSynchronize(stream_));
+    dfree(d_where);
+    dfree(d_old);
     dfree(v64_tmp);
     dfree(v_tmp);
     dfree(src_out);
@@ -1344,6 +1415,7 @@ void Engine<T>::sort_blocks(int id, bool dual) {
     dfree(d_blk);
     dfree(d_all);
   }
+  (dual ? S.plainD : S.plainP) = sorted.empty() ? 0 : rows;
   if (dual) S.bD = out;
   else S.bP = out;
 }
@@ -1906,6 +1978,7 @@ void Engine<T>::run(double time_limit_s) {
         HIPCHECK(hipMemcpy(h_status[0], d_status, sizeof(int) * nslots_, hipMemcpyDeviceToHost));
         std::memcpy(h_status[1], h_status[0], sizeof(int) * nslots_);
         finished_ = h_status[0];
+        reblock_for(h_status[0]);
         rebuild_schedules();
         finished_ = nullptr;
         sched_dirty_ = true;  // the next add / remove / solve rebuilds the full schedules

@@ -1,0 +1,236 @@
+// Kernels that build the matrix layouts at lp_create (and when a batch
+// re-blocks its last LPs): the explicit transpose K^T, column slicing, the
+// sort keys of column-sorted blocks and groups and the gathers that apply a
+// sorted permutation.  None of them runs in a solver step.  Included by
+// engine.hip after kernels.hip (shared types from halp_types.h).
+
+namespace halp {
+
+__global__ void shift_copy_kernel(int32_t* dst, const int32_t* src, int64_t n, int64_t add) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (int32_t)(src[i] + add);
+}
+
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+// rowid[e - z0] = row, for every entry of the rows in the dual schedule
+__global__ __launch_bounds__(kThreads) void row_ids_kernel(const Blk* sched, const int32_t* rp,
+                                                           int64_t z0, int32_t* rowid) {
+  const Blk b = sched[blockIdx.x];
+  const int nrows = b.r1 - b.r0;
+  const int G = (blk_kind(b) == BK_LONG) ? kThreads : group_size(nrows);
+  const int lane = threadIdx.x & (G - 1);
+  for (int base = 0; base < nrows; base += kThreads / G) {
+    const int r = base + threadIdx.x / G;
+    if (r >= nrows) continue;
+    const int row = b.r0 + r;
+    const int p1 = rp[row + 1];
+    for (int e = rp[row] + lane; e < p1; e += G) rowid[e - z0] = row;
+  }
+}
+
+// cnt[(r - r0) * kSlices + s] = entries of row r whose column lies in slice s
+// of the gathered range [c0, c0 + len)
+__global__ void slice_count_kernel(const int32_t* rp, const int32_t* ci, int64_t r0, int64_t nrows,
+                                   int64_t c0, int64_t len, int nsl, int32_t* cnt) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int32_t c[kSlices];
+  for (int q = 0; q < kSlices; ++q) c[q] = 0;
+  for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
+    const int q = (int)(((int64_t)(ci[e] - c0) * nsl) / len);
+    c[q] += 1;
+  }
+  for (int q = 0; q < nsl; ++q) cnt[r * nsl + q] = c[q];
+}
+
+// Scatter row r's entries to their slice-major positions: dst[(r - r0) *
+// kSlices + s] is the first position of row r's slice-s entries.
+template <class V>
+__global__ void slice_scatter_kernel(const int32_t* rp, const int32_t* ci, const V* val, const double* v64,
+                                     int64_t r0, int64_t nrows, int64_t c0, int64_t len, const int32_t* dst,
+                                     int32_t* ci_out, V* val_out, double* v64_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int32_t d[kSlices];
+  for (int q = 0; q < kSlices; ++q) d[q] = dst[r * kSlices + q];
+  for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
+    const int q = (int)(((int64_t)(ci[e] - c0) * kSlices) / len);
+    const int32_t p = d[q]++;
+    ci_out[p] = ci[e];
+    val_out[p] = val[e];
+    if (v64_out) v64_out[p] = v64[e];
+  }
+}
+
+// Sorted slicing, step 1: row r's entries go to their row-major positions
+// in the sorted groups (dst as for slice_scatter_kernel), each with its sort
+// key (column - first column of its slice) << rb | (r - first row of the
+// group) and the position it came from.
+__global__ void slice_keys_kernel(const int32_t* rp, const int32_t* ci, int64_t r0, int64_t nrows, int64_t c0,
+                                  int64_t len, int nsl, const int32_t* dst, const int32_t* rloc, int rb,
+                                  uint32_t* key_out, int32_t* src_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  int32_t d[kSlices];
+  for (int q = 0; q < nsl; ++q) d[q] = dst[r * nsl + q];
+  for (int32_t e = rp[r0 + r]; e < rp[r0 + r + 1]; ++e) {
+    const int64_t c = ci[e] - c0;
+    const int q = (int)((c * nsl) / len);
+    const int64_t first = (q * len + nsl - 1) / nsl;
+    const int32_t p = d[q]++;
+    key_out[p] = ((uint32_t)(c - first) << rb) | (uint32_t)rloc[r];
+    src_out[p] = e;
+  }
+}
+
+// Column-sorting of plain blocks, step 1: for every entry of every block of
+// one LP's schedule (blocks in position order, covering its entries), a
+// 64-bit sort key with the block's index in the high word and, in the low
+// word, (column - b.rp_off) << rb | (row - b.r0) for a BK_SORTED block, the
+// entry's index in the block for any other (so that it stays in place), and
+// the entry's position.  Positions are relative to nz0 in the key arrays.
+__global__ __launch_bounds__(kThreads) void block_keys_kernel(const Blk* blks, const int32_t* rp,
+                                                              const int32_t* ci, int64_t nz0, uint64_t* key,
+                                                              int32_t* src) {
+  const Blk b = blks[blockIdx.x];
+  const uint64_t hi = (uint64_t)blockIdx.x << 32;
+  if (blk_kind(b) == BK_SORTED) {
+    const int rb = blk_rowbits(b);
+    const int nrows = b.r1 - b.r0;
+    for (int r = threadIdx.x; r < nrows; r += kThreads) {
+      for (int32_t e = rp[b.r0 + r]; e < rp[b.r0 + r + 1]; ++e) {
+        key[e - nz0] = hi | (((uint32_t)(ci[e] - b.rp_off) << rb) | (uint32_t)r);
+        src[e - nz0] = e;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < b.pn; e += kThreads) {
+      const int64_t p = (int64_t)b.p0 + e;
+      key[p - nz0] = hi | (uint32_t)e;
+      src[p - nz0] = (int32_t)p;
+    }
+  }
+}
+
+// Re-blocking of a product stored in column-sorted blocks: every entry of
+// the old blocks `old` (which cover the LP's entries) gets the key of its
+// place in the new blocks, where[row - base] = (new block index, row in that
+// block).  BK_SORTED entries read their row and column back from the packed
+// key (the column relative to b.rp_off, which the new blocks share); BK_LONG
+// entries (rows that stay long) keep their order.
+__global__ __launch_bounds__(kThreads) void reblock_keys_kernel(const Blk* old, const int2* where, int64_t base,
+                                                                int rb_new, const int32_t* ci, int64_t nz0,
+                                                                uint64_t* key, int32_t* src) {
+  const Blk b = old[blockIdx.x];
+  if (blk_kind(b) == BK_SORTED) {
+    const int rb = blk_rowbits(b);
+    const uint32_t rmask = (1u << rb) - 1u;
+    for (int e = threadIdx.x; e < b.pn; e += kThreads) {
+      const int64_t p = (int64_t)b.p0 + e;
+      const uint32_t w = (uint32_t)ci[p];
+      const int2 t = where[b.r0 + (int64_t)(w & rmask) - base];
+      key[p - nz0] = ((uint64_t)(uint32_t)t.x << 32) | (((w >> rb) << rb_new) | (uint32_t)t.y);
+      src[p - nz0] = (int32_t)p;
+    }
+  } else {
+    const uint64_t hi = (uint64_t)(uint32_t)where[b.r0 - base].x << 32;
+    for (int e = threadIdx.x; e < b.pn; e += kThreads) {
+      const int64_t p = (int64_t)b.p0 + e;
+      key[p - nz0] = hi | (uint32_t)e;
+      src[p - nz0] = (int32_t)p;
+    }
+  }
+}
+
+// Step 2 (after the keys are sorted): the entries of every BK_SORTED block
+// take the low words of the sorted keys as packed column indices and the
+// values of the entries they came from (values staged in v_tmp / v64_tmp,
+// relative to nz0).
+template <class V>
+__global__ __launch_bounds__(kThreads) void sorted_block_gather_kernel(const Blk* blks, int64_t nz0,
+                                                                       const uint64_t* key, const int32_t* src,
+                                                                       const V* val, const double* v64,
+                                                                       int32_t* ci_out, V* v_tmp,
+                                                                       double* v64_tmp) {
+  const Blk b = blks[blockIdx.x];
+  for (int e = threadIdx.x; e < b.pn; e += kThreads) {
+    const int64_t p = (int64_t)b.p0 + e;
+    const int64_t rel = p - nz0;
+    const int32_t from = src[rel];
+    ci_out[p] = (int32_t)(uint32_t)key[rel];
+    v_tmp[rel] = val[from];
+    if (v64_tmp) v64_tmp[rel] = v64[from];
+  }
+}
+
+// Sorted groups: the key of every entry gets its (group, slice) block's
+// index in the high word; block s holds positions [off[s], off[s + 1]).
+__global__ __launch_bounds__(kThreads) void segment_keys_kernel(const int32_t* off, const uint32_t* k32,
+                                                                uint64_t* k64) {
+  const int s = blockIdx.x;
+  const uint64_t hi = (uint64_t)s << 32;
+  for (int64_t p = off[s] + threadIdx.x; p < off[s + 1]; p += kThreads) k64[p] = hi | k32[p];
+}
+
+// Sorted slicing, step 2 (after the keys are sorted within each block):
+// entry p takes the sorted key as its packed column index and the value of
+// the entry it came from.
+template <class V>
+__global__ void sorted_gather_kernel(const uint64_t* key, const int32_t* src, const V* val, const double* v64,
+                                     int64_t nnz, int32_t* ci_out, V* val_out, double* v64_out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t e = src[p];
+  ci_out[p] = (int32_t)(uint32_t)key[p];
+  val_out[p] = val[e];
+  if (v64_out) v64_out[p] = v64[e];
+}
+
+template <class V>
+__global__ void transpose_gather_kernel(const int32_t* perm, const int32_t* rowid, const V* val,
+                                        int64_t z0, int64_t nnz, int32_t* kt_ci, V* kt_val) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t e = perm[p];
+  kt_ci[z0 + p] = rowid[e];
+  kt_val[z0 + p] = val[z0 + e];
+}
+
+// kt_rp[j] = z0 + #{sorted keys < j - c0} for space positions j in [c0, c1]
+// (keys: columns relative to c0)
+__global__ void transpose_rowptr_kernel(const uint32_t* keys, int64_t nnz, int64_t z0, int64_t c0,
+                                        int64_t c1, int32_t* kt_rp) {
+  const int64_t j = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > c1) return;
+  int64_t lo = 0, hi = nnz;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] + c0 < j) lo = mid + 1; else hi = mid;
+  }
+  kt_rp[j] = (int32_t)(z0 + lo);
+}
+
+template __global__ void sorted_block_gather_kernel<double>(const Blk*, int64_t, const uint64_t*,
+                                                            const int32_t*, const double*, const double*,
+                                                            int32_t*, double*, double*);
+template __global__ void sorted_block_gather_kernel<float>(const Blk*, int64_t, const uint64_t*,
+                                                           const int32_t*, const float*, const double*,
+                                                           int32_t*, float*, double*);
+template __global__ void sorted_gather_kernel<double>(const uint64_t*, const int32_t*, const double*,
+                                                      const double*, int64_t, int32_t*, double*, double*);
+template __global__ void sorted_gather_kernel<float>(const uint64_t*, const int32_t*, const float*,
+                                                     const double*, int64_t, int32_t*, float*, double*);
+template __global__ void slice_scatter_kernel<double>(const int32_t*, const int32_t*, const double*,
+                                                      const double*, int64_t, int64_t, int64_t, int64_t,
+                                                      const int32_t*, int32_t*, double*, double*);
+template __global__ void slice_scatter_kernel<float>(const int32_t*, const int32_t*, const float*,
+                                                     const double*, int64_t, int64_t, int64_t, int64_t,
+                                                     const int32_t*, int32_t*, float*, double*);
+template __global__ void transpose_gather_kernel<double>(const int32_t*, const int32_t*, const double*,
+                                                         int64_t, int64_t, int32_t*, double*);
+
+}  // namespace halp
