@@ -781,6 +781,9 @@ struct lp_server {
   double* dbuf = nullptr;  // device staging of candidates between the phases
   int64_t dbuf_len = 0;
   int64_t admit_nz = 0, admit_nz64 = 0;  // stored entries one admission may add to each engine
+  // live LPs of each engine when its layouts were last sized: once half of
+  // them have retired the rest are re-blocked for fewer LPs per launch
+  int refine_live = 0, refine_live64 = 0;
   double t0 = 0.0;
   double clock() const { return now_s() - t0; }
   ~lp_server() {
@@ -955,6 +958,8 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
         s->slot_ticket64[id] = t;
       }
     }
+    s->refine_live = std::max(s->refine_live, s->eng->live());
+    if (s->eng64) s->refine_live64 = std::max(s->refine_live64, s->eng64->live());
     int nd = 0;
     if (s->eng->live() > 0 && chunks > 0) {
       std::vector<int> done = s->eng->advance(chunks);
@@ -1001,6 +1006,17 @@ int lp_server_step(lp_server* s, int chunks, int* n_done) {
         ++nd;
       }
     }
+    auto refine = [](halp::EngineBase& e, int& at) {
+      const int live = e.live();
+      if (live > 0 && 2 * live <= at) {
+        e.refine_layouts();
+        at = live;
+      } else if (live == 0) {
+        at = 0;
+      }
+    };
+    refine(*s->eng, s->refine_live);
+    if (s->eng64) refine(*s->eng64, s->refine_live64);
     if (n_done) *n_done = nd;
     return LP_OK;
   });

@@ -138,6 +138,9 @@ class EngineBase {
   // host arrays; only while that product is stored in row order (no column
   // slices, no column-sorted blocks or groups), else Error(-4)
   virtual void stored_matrix(int id, bool transpose, int32_t* rp, int32_t* ci, double* val) = 0;
+  // smaller column-sorted blocks for the LPs still running (by the statuses
+  // of the last advance) when few of them share the launches
+  virtual void refine_layouts() = 0;
 };
 
 // Size of the static device workspace of the allocation-free entry point.

@@ -303,17 +303,31 @@ static void build_sliced(const int32_t* cnt, int64_t nrows, int64_t base, int in
 
 // Blocks per product of a column-sorted LP: at least kMinSortedBlocks (rows
 // down to kMaxRows) in engines of many LPs, whose products share each
-// launch; at least kMinSortedBlocksAlone (rows down to kMinSortedRows) for an
-// LP that runs alone, where the product's blocks are all the launch has
-// (measured on MI355X, LPs of 12.8k and 18.6k rows alone: 21.4 and 36.8 us
-// per iteration with 256-row blocks, 13.0 and 17.5 us with 128-row blocks;
-// in a batch of 512 such LPs 64-row blocks everywhere cost 7% over the
-// default).  A batch re-blocks its remaining LPs when few are left.
+// launch; for an LP among few, enough that the engine's products have about
+// kTailBlocks workgroups (rows down to kMinSortedRows), since its blocks are
+// most of what the launch has (measured on MI355X, LPs of 12.8k and 18.6k
+// rows alone: 21.4 and 36.8 us per iteration with 256-row blocks, 13.0 and
+// 17.5 us with 128-row blocks; in a batch of 512 such LPs 64-row blocks
+// everywhere cost 7% over the default).  Engines re-block their running LPs
+// as LPs finish (refine_layouts).
 constexpr int64_t kMinSortedBlocks = 64;
-constexpr int64_t kMinSortedBlocksAlone = 192;
 constexpr int64_t kMinSortedRows = 64;
-// a batch's products keep at least this many workgroups as LPs finish
+// the products of an engine with few LPs keep at least this many
+// workgroups in all: blocks are sized for the LPs that share the launches
 constexpr int64_t kTailBlocks = 768;
+
+// Blocks per product (at least) and smallest row cap of the column-sorted
+// blocks of an LP that shares the launches with `live` LPs in all.
+static void plain_shape(int64_t live, int64_t* min_blocks, int64_t* min_rows) {
+  live = std::max<int64_t>(live, 1);
+  if (live * kMinSortedBlocks >= kTailBlocks) {
+    *min_blocks = kMinSortedBlocks;
+    *min_rows = kMaxRows;
+  } else {
+    *min_blocks = (kTailBlocks + live - 1) / live;
+    *min_rows = kMinSortedRows;
+  }
+}
 
 struct Slot {
   bool used = false;
@@ -389,6 +403,10 @@ class Engine final : public EngineBase {
   void certificate(int id, double* ray, bool to_device) override;
   void export_point(int id, double* x, double* y, double* omega) override;
   void stored_matrix(int id, bool transpose, int32_t* rp, int32_t* ci, double* val) override;
+  void refine_layouts() override {
+    HIPCHECK(hipStreamSynchronize(stream_));
+    reblock_for(h_status[0]);
+  }
   void import_point(int id, const double* x, const double* y, double omega) override;
 
  private:
@@ -972,6 +990,7 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
   // block holds is stored in sorted groups of 1 or 2 slices (larger groups:
   // more entries share each cache line of the gathered vector).  The other
   // products get column-sorted plain blocks (plain_sort) or plain tiles.
+  const int64_t live_after = live();
   for (int id : ids) {
     const Slot& S = slots_[id];
     for (const bool dual : {true, false}) {
@@ -991,8 +1010,9 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
                  (slice || rows > std::min<int64_t>(opt_.sort_rows, kSortRowsPlain))) {
         group_sorted(id, dual, nsl, rows);
       } else if (opt_.plain_sort) {
-        sort_blocks(id, dual, nslots_ == 1 ? kMinSortedBlocksAlone : kMinSortedBlocks,
-                    nslots_ == 1 ? kMinSortedRows : kMaxRows, false);
+        int64_t minb = 0, minr = 0;
+        plain_shape(live_after, &minb, &minr);
+        sort_blocks(id, dual, minb, minr, false);
       }
     }
   }
@@ -1259,27 +1279,31 @@ int64_t Engine<T>::plain_rows(int64_t nrows, int64_t width, int64_t min_blocks, 
 }
 
 // Smaller column-sorted blocks for the LPs still running (status) when few
-// are left: each gets at least kTailBlocks / (running LPs) blocks per
-// product, down to kMinSortedRows rows, so that the launches keep the CUs
-// busy.  Products in sorted groups, column slices or plain tiles keep their
-// layout.
+// are left (plain_shape for their number), so that the launches keep the
+// CUs busy.  Products in sorted groups, column slices or plain tiles keep
+// their layout.
 template <class T>
 void Engine<T>::reblock_for(const int* status) {
   std::vector<int> run;
   for (int s = 0; s < nslots_; ++s)
     if (slots_[s].used && status[s] == ST_RUNNING) run.push_back(s);
   if (run.empty()) return;
-  const int64_t minb = (kTailBlocks + (int64_t)run.size() - 1) / (int64_t)run.size();
+  int64_t minb = 0, minr = 0;
+  plain_shape((int64_t)run.size(), &minb, &minr);
+  bool changed = false;
   for (int s : run) {
     for (int d = 0; d < 2; ++d) {
       const bool dual = d == 1;
       const Slot& S = slots_[s];
       const int64_t cur = dual ? S.plainD : S.plainP;
       if (cur == 0) continue;
-      if (plain_rows(dual ? S.m : S.n, dual ? S.n : S.m, minb, kMinSortedRows) < cur)
-        sort_blocks(s, dual, minb, kMinSortedRows, true);
+      if (plain_rows(dual ? S.m : S.n, dual ? S.n : S.m, minb, minr) < cur) {
+        sort_blocks(s, dual, minb, minr, true);
+        changed = true;
+      }
     }
   }
+  if (changed) sched_dirty_ = true;
 }
 
 // Column-sorted blocks of one LP's K (dual = true) or K^T, for a product
