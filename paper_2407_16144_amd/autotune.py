@@ -7,14 +7,19 @@ once per candidate shape, runs a fixed number of steps with every chunk
 timed by HIP events (their own cost taken out), and returns the shape with
 the least kernel time per step.
 
-Search (coordinate descent, 4 + 6 candidates):
-  1. the unsliced products (Kᵀ of the large LP, every product of small LPs):
-     column-sorted blocks with the default sort_rows (2048 rows per plain
-     block, 4096 per slice group) or sort_rows 1024, or fixed-order plain
-     tiles (plain_sort 0) of tile_rows in {128, 256};
-  2. only if the LP has a column-sliced product, with the best of step 1:
-     fixed-order slices (slice_sort 0) with slice_entries in {256, 512,
-     1024} x slice_rows in {64, 128}.
+Search (coordinate descent, 5 + 4 + 6 candidates):
+  1. the products in column-sorted plain blocks or plain tiles (every
+     product of small LPs, K^T of some large ones): plain blocks with the
+     default row cap (sized for the LPs that share the launches, at most
+     2048 rows) or sort_rows 1024 or 128, or fixed-order plain tiles
+     (plain_sort 0) of tile_rows in {128, 256};
+  2. only if the LP has a product with a slice kernel (sorted groups, the
+     default for products whose gathered vector exceeds slice_min_bytes or
+     whose groups can hold more rows than a plain block), with the best of
+     step 1: sorted groups with group_threads in {256, 512, 1024} (the
+     default picks one for about eight waves per CU) or unbatched gathers
+     (group_batched 0), then fixed-order slices (slice_sort 0) with
+     slice_entries in {256, 512, 1024} x slice_rows in {64, 128}.
 
 Each candidate's solve starts from scratch and its iterates are discarded;
 the chosen options are then passed to the real solve.
@@ -27,7 +32,9 @@ from . import (lp_create, lp_default_options, lp_destroy, lp_kernel_times, lp_so
                make_problems, lp_batch_create_from, lp_batch_solve, lp_batch_kernel_times,
                lp_batch_destroy)
 
-FIRST = ({}, {"sort_rows": 1024}, {"plain_sort": 0, "tile_rows": 128}, {"plain_sort": 0, "tile_rows": 256})
+FIRST = ({}, {"sort_rows": 1024}, {"sort_rows": 128}, {"plain_sort": 0, "tile_rows": 128},
+         {"plain_sort": 0, "tile_rows": 256})
+GROUP_SHAPES = ({"group_threads": 256}, {"group_threads": 512}, {"group_threads": 1024}, {"group_batched": 0})
 SLICE_SHAPES = tuple((e, r) for e in (256, 512, 1024) for r in (64, 128))
 
 
@@ -91,7 +98,8 @@ def autotune(lp_or_lps, iters: int = 640, stream=None, **base):
         if ms < best_ms:
             best, best_ms = dict(shape), ms
     if sliced:
-        cands = [{**best, "slice_sort": 0, "slice_entries": e, "slice_rows": r} for e, r in SLICE_SHAPES]
+        cands = [{**best, **g} for g in GROUP_SHAPES]
+        cands += [{**best, "slice_sort": 0, "slice_entries": e, "slice_rows": r} for e, r in SLICE_SHAPES]
         for shape in cands:
             ms, _ = measure(shape)
             if ms < best_ms:

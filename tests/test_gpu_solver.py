@@ -831,7 +831,7 @@ def test_autotune_picks_a_measured_shape():
     lp = lpgen.scaled_powerlaw(21, 500, 1800)
     print("case autotune", flush=True)
     best, table, secs = autotune.autotune(lp, iters=256, slice_min_bytes=0)
-    assert len(table) == len(autotune.FIRST) + len(autotune.SLICE_SHAPES)
+    assert len(table) == len(autotune.FIRST) + len(autotune.GROUP_SHAPES) + len(autotune.SLICE_SHAPES)
     assert best in [shape for shape, _ in table]
     assert all(ms > 0 for _, ms in table)
     r, x, y, _ = _gpu(lp, 1e-4, 100_000, slice_min_bytes=0, **best)
