@@ -393,6 +393,48 @@ def test_fp32_stall_rule_hands_over_to_fp64():
     assert kkt <= 5e-10 * (1 + 1e-6), parts
 
 
+def _trivial_lp():
+    """x = 1 (one equality row, one variable): optimal at the first checks."""
+    return lpgen.LP(n=1, m_eq=1, m_ineq=0, rowptr=np.array([0, 1], np.int32), col=np.array([0], np.int32),
+                    val=np.array([1.0]), c=np.array([1.0]), rhs=np.array([1.0]), lb=np.zeros(1),
+                    ub=np.full(1, 10.0))
+
+
+def test_batch_reblocks_its_last_lps():
+    """A batch of 6 LPs of 2-4k rows and 12 trivial LPs sizes its
+    column-sorted blocks for 18 LPs sharing each launch (256-row blocks);
+    once the trivial LPs are optimal it compacts its schedules and re-sorts
+    the 6 still running into the smaller blocks (64 rows) sized for 6 LPs,
+    mid-run.  Their iterates after 1,600 evaluations equal those of the 6
+    LPs batched alone (blocks of that size from the start) and, for one of
+    them, the oracle's, to 1e-10 element by element: the re-sorted layout
+    holds the same matrix."""
+    big = [lpgen.scaled_powerlaw(700 + i, m, 4 * m) for i, m in enumerate([2000, 3000, 4000, 2500, 3500, 2200])]
+    lps = big + [_trivial_lp() for _ in range(12)]
+    iters = 1600
+    print("case batch reblock", flush=True)
+    out = {}
+    for name, group in (("mixed", lps), ("alone", big)):
+        h = halp.lp_batch_create(group)
+        try:
+            halp.lp_batch_solve(h, 1e-9, iters)
+            out[name] = [(halp.lp_batch_status(h, i).as_dict(), halp.lp_batch_get_solution(h, i, lp.n, lp.m))
+                         for i, lp in enumerate(group)]
+        finally:
+            halp.lp_batch_destroy(h)
+    for i in range(len(big), len(lps)):
+        assert out["mixed"][i][0]["status"] == halp.LP_OPTIMAL and out["mixed"][i][0]["iters"] < iters // 2
+    for i in range(len(big)):
+        ra, (xa, ya) = out["mixed"][i]
+        rb, (xb, yb) = out["alone"][i]
+        assert ra["status"] == rb["status"] == halp.LP_ITER_LIMIT and ra["iters"] == rb["iters"]
+        assert ra["restarts"] == rb["restarts"], (ra, rb)
+        assert _rel(xa, xb) <= 1e-10 and _rel(ya, yb) <= 1e-10, i
+    ref = oracle.solve(big[0], oracle.Options(tol=0.0, max_iter=out["mixed"][0][0]["iters"]))
+    assert ref.iters == out["mixed"][0][0]["iters"]
+    assert _rel(out["mixed"][0][1][0], ref.x) <= 1e-10 and _rel(out["mixed"][0][1][1], ref.y) <= 1e-10
+
+
 def test_fp32_phase_cap_without_stall_rule():
     """With the stall rule off, the FP32 phase of a polished solve runs until
     its cap, a tenth of max_iter (honoured at check granularity), and the
