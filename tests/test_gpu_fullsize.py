@@ -24,6 +24,12 @@ hipGraph chunks of 64 steps).
   error does not bound the objective error by itself (on this LP a point
   whose dual residual is 1.5e-5 of 1 + ||c|| lies 4e-3 from the optimum);
   the check holds because the FP64 phase carries the FP32 phase's weight.
+* Batch of 512 power-law LPs (74M nnz, 10% planted infeasible), solved as
+  one batch in FP64 to 1e-4 as the benchmark does: every planted
+  infeasible LP, and no other, ends PRIMAL_INFEASIBLE with a ray that the
+  oracle's Farkas test accepts; every other LP ends OPTIMAL with the
+  relative KKT error, recomputed by the oracle from the returned point,
+  within the tolerance (all 512 checked).
 """
 import numpy as np
 import pytest
@@ -118,3 +124,36 @@ def test_mixed_fp32_polish_reaches_tolerance(mixed):
     assert abs(kkt - res["rel_kkt"]) <= 1e-8
     # not implied by the tolerance (see above); measured 1.9e-5
     assert dobj <= tol
+
+
+@pytest.mark.timeout(900)
+def test_batch_512_statuses_certificates_and_kkt():
+    tol = 1e-4
+    print("case batch 512", flush=True)
+    m, n, infeasible = lpgen.batch_sizes(lpgen.BASE_SEED + 3, 512)
+    lps = lpgen.batch(512)
+    h = halp.lp_batch_create(lps)
+    try:
+        halp.lp_batch_solve(h, tol, 2_000_000)
+        results = []
+        for i, lp in enumerate(lps):
+            r = halp.lp_batch_status(h, i).as_dict()
+            if r["status"] == halp.LP_PRIMAL_INFEASIBLE:
+                results.append((r, None, halp.lp_batch_get_certificate(h, i, lp.m)))
+            else:
+                results.append((r, halp.lp_batch_get_solution(h, i, lp.n, lp.m), None))
+    finally:
+        halp.lp_batch_destroy(h)
+    worst = 0.0
+    for i, (lp, (r, sol, ray)) in enumerate(zip(lps, results)):
+        if infeasible[i]:
+            assert r["status"] == halp.LP_PRIMAL_INFEASIBLE, (i, r)
+            ok, info = oracle.primal_ray_check(lp, ray)
+            assert ok, (i, info)
+        else:
+            assert r["status"] == halp.LP_OPTIMAL, (i, r)
+            kkt, parts = oracle.rel_kkt(lp, *sol)
+            assert kkt <= tol * (1 + 1e-6), (i, parts)
+            worst = max(worst, kkt)
+    print(f"batch 512: {int(infeasible.sum())} certified infeasible, {int((~infeasible).sum())} optimal, "
+          f"largest recomputed KKT {worst:.3e}", flush=True)
