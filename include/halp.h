@@ -339,6 +339,11 @@ int lp_server_step(lp_server* s, int chunks, int* n_done);
 int lp_server_poll(lp_server* s, int64_t ticket, int* done, lp_result* out, double* t_done);
 /* The finished ticket's unscaled solution (host memory). */
 int lp_server_get_solution(lp_server* s, int64_t ticket, double* x, double* y);
+/* The finished ticket's certificate, as lp_get_certificate (host memory:
+ * m entries after LP_PRIMAL_INFEASIBLE, n after LP_DUAL_INFEASIBLE);
+ * LP_ERR_STATE for a ticket that is not finished or was not found
+ * infeasible. */
+int lp_server_get_certificate(lp_server* s, int64_t ticket, double* ray);
 /* Forget a finished ticket. */
 int lp_server_release(lp_server* s, int64_t ticket);
 /* The server's clock: seconds since lp_server_create (use it for t_arrival). */

@@ -105,6 +105,7 @@ _sig = {
     "lp_server_step": (C.c_int, [_P, C.c_int, _P]),
     "lp_server_poll": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
     "lp_server_get_solution": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "lp_server_get_certificate": (C.c_int, [_P, C.c_int64, _P]),
     "lp_server_release": (C.c_int, [_P, C.c_int64]),
     "lp_server_clock": (C.c_int, [_P, _P]),
     "lp_server_info": (C.c_int, [_P, _P, _P, _P]),
@@ -342,6 +343,12 @@ def lp_server_get_solution(h, ticket, n, m):
     y = np.empty(max(m, 1))
     _check(_lib.lp_server_get_solution(h, int(ticket), x.ctypes.data, y.ctypes.data))
     return x[:n], y[:m]
+
+
+def lp_server_get_certificate(h, ticket, length):
+    r = np.empty(max(length, 1))
+    _check(_lib.lp_server_get_certificate(h, int(ticket), r.ctypes.data))
+    return r[:length]
 
 
 def lp_server_release(h, ticket):

@@ -710,6 +710,7 @@ struct Request {
   lp_result res{};
   double t_done = 0.0;
   std::vector<double> x, y;
+  std::vector<double> ray;  // certificate of an infeasible request (m or n entries)
   // FP32 server with polish: the FP32 phase's candidate (scaled) and result,
   // and the slot of the FP64 phase
   std::vector<double> px, py;
@@ -886,6 +887,10 @@ void finish_request(lp_server* s, Request& r, halp::EngineBase& eng, int slot, c
   r.x.resize(r.n);
   r.y.resize(r.m_eq + r.m_ineq);
   eng.solution(slot, r.x.data(), r.y.empty() ? nullptr : r.y.data(), false);
+  if (res.status == LP_PRIMAL_INFEASIBLE || res.status == LP_DUAL_INFEASIBLE) {
+    r.ray.resize(res.status == LP_PRIMAL_INFEASIBLE ? r.m_eq + r.m_ineq : r.n);
+    if (!r.ray.empty()) eng.certificate(slot, r.ray.data(), false);
+  }
   r.t_done = tnow;
   r.done = true;
   r.slot = r.slot64 = -1;
@@ -1044,6 +1049,21 @@ int lp_server_get_solution(lp_server* s, int64_t ticket, double* x, double* y) {
     if (!it->second.done) return fail(LP_ERR_STATE, "ticket not finished");
     if (x) std::memcpy(x, it->second.x.data(), sizeof(double) * it->second.x.size());
     if (y && !it->second.y.empty()) std::memcpy(y, it->second.y.data(), sizeof(double) * it->second.y.size());
+    return LP_OK;
+  });
+}
+
+int lp_server_get_certificate(lp_server* s, int64_t ticket, double* ray) {
+  return guarded([&]() -> int {
+    if (!s || !ray) return fail(LP_ERR_INVALID, "null argument");
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(LP_ERR_INVALID, "unknown ticket");
+    if (!it->second.done) return fail(LP_ERR_STATE, "ticket not finished");
+    const int st = it->second.res.status;
+    if (st != LP_PRIMAL_INFEASIBLE && st != LP_DUAL_INFEASIBLE)
+      return fail(LP_ERR_STATE, "no certificate: the request was not found infeasible");
+    if (!it->second.ray.empty())
+      std::memcpy(ray, it->second.ray.data(), sizeof(double) * it->second.ray.size());
     return LP_OK;
   });
 }

@@ -170,6 +170,7 @@ static void null_handles(void) {
   EXPECT(lp_server_step(NULL, 1, &done) == LP_ERR_INVALID, "lp_server_step(NULL)");
   EXPECT(lp_server_poll(NULL, 1, &done, &r, &t) == LP_ERR_INVALID, "lp_server_poll(NULL)");
   EXPECT(lp_server_get_solution(NULL, 1, x, y) == LP_ERR_INVALID, "lp_server_get_solution(NULL)");
+  EXPECT(lp_server_get_certificate(NULL, 1, x) == LP_ERR_INVALID, "lp_server_get_certificate(NULL)");
   EXPECT(lp_server_release(NULL, 1) == LP_ERR_INVALID, "lp_server_release(NULL)");
   EXPECT(lp_server_clock(NULL, &t) == LP_ERR_INVALID, "lp_server_clock(NULL)");
   EXPECT(lp_server_info(NULL, &q, &live, &bytes) == LP_ERR_INVALID, "lp_server_info(NULL)");

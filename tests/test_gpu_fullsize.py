@@ -30,6 +30,13 @@ hipGraph chunks of 64 steps).
   oracle's Farkas test accepts; every other LP ends OPTIMAL with the
   relative KKT error, recomputed by the oracle from the returned point,
   within the tolerance (all 512 checked).
+* The first 100 requests of the serving trace (Poisson arrivals at
+  200 LP/s, 2% large, 5% infeasible, 2% unbounded), all submitted at once to
+  one server of 512 slots as the benchmark's overloaded run has them: every
+  feasible request ends OPTIMAL with the oracle-recomputed KKT error within
+  1e-4, every infeasible one PRIMAL_INFEASIBLE with a ray the oracle's
+  Farkas test accepts, every unbounded one DUAL_INFEASIBLE with a valid ray
+  (or, for the requests on which the method stalls, at the iteration limit).
 """
 import numpy as np
 import pytest
@@ -157,3 +164,56 @@ def test_batch_512_statuses_certificates_and_kkt():
             worst = max(worst, kkt)
     print(f"batch 512: {int(infeasible.sum())} certified infeasible, {int((~infeasible).sum())} optimal, "
           f"largest recomputed KKT {worst:.3e}", flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_serving_trace_first_100_requests():
+    tol, max_iter = 1e-4, 2_000_000      # the benchmark's budget: some requests need over 300k
+    trace = lpgen.serving_trace(count=100)
+    lps = [lpgen.request_instance(r) for r in trace]
+    print("case serving trace 100", flush=True)
+    h = halp.lp_server_create(64 * 10**9, 512)
+    out = {}
+    try:
+        tickets = {halp.lp_server_submit(h, lp, tol, max_iter, r.t_arrival): i
+                   for i, (lp, r) in enumerate(zip(lps, trace))}
+        for _ in range(1_000_000):
+            if not tickets:
+                break
+            halp.lp_server_step(h, 2)
+            for tk, i in list(tickets.items()):
+                r, _ = halp.lp_server_poll(h, tk)
+                if r is None:
+                    continue
+                r = r.as_dict()
+                lp = lps[i]
+                if r["status"] == halp.LP_PRIMAL_INFEASIBLE:
+                    extra = halp.lp_server_get_certificate(h, tk, lp.m)
+                elif r["status"] == halp.LP_DUAL_INFEASIBLE:
+                    extra = halp.lp_server_get_certificate(h, tk, lp.n)
+                else:
+                    extra = halp.lp_server_get_solution(h, tk, lp.n, lp.m)
+                out[i] = (r, extra)
+                halp.lp_server_release(h, tk)
+                del tickets[tk]
+        assert not tickets
+    finally:
+        halp.lp_server_destroy(h)
+    kinds = {}
+    for i, (req, lp) in enumerate(zip(trace, lps)):
+        r, extra = out[i]
+        kinds.setdefault(req.kind, []).append(r["status"])
+        if req.kind == "infeasible":
+            assert r["status"] == halp.LP_PRIMAL_INFEASIBLE, (i, r)
+            ok, info = oracle.primal_ray_check(lp, extra)
+            assert ok, (i, info)
+        elif req.kind == "unbounded":
+            assert r["status"] in (halp.LP_DUAL_INFEASIBLE, halp.LP_ITER_LIMIT), (i, r)
+            if r["status"] == halp.LP_DUAL_INFEASIBLE:
+                ok, info = oracle.dual_ray_check(lp, extra)
+                assert ok, (i, info)
+        else:
+            assert r["status"] == halp.LP_OPTIMAL, (i, req.kind, r)
+            kkt, parts = oracle.rel_kkt(lp, *extra)
+            assert kkt <= tol * (1 + 1e-6), (i, parts)
+    print("statuses by kind", {k: {s: v.count(s) for s in set(v)} for k, v in kinds.items()}, flush=True)
