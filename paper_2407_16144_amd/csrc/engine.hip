@@ -811,8 +811,11 @@ std::vector<int> Engine<T>::add(const std::vector<Problem>& probs_in, bool on_de
       int* d_flags = nullptr;
       dalloc(&d_flags, 1);
       HIPCHECK(hipMemsetAsync(d_flags, 0, sizeof(int), stream_));
-      if (m > 0)
-        validate_csr_kernel<<<nblk(m), 256, 0, stream_>>>(p.rp, p.ci, p.val, m, p.n, ends[1], d_flags);
+      if (m > 0) {
+        validate_rowptr_kernel<<<nblk(m), 256, 0, stream_>>>(p.rp, m, ends[1], d_flags);
+        if (ends[1] > 0)
+          validate_entries_kernel<<<nblk(ends[1]), 256, 0, stream_>>>(p.rp, p.ci, p.val, m, p.n, ends[1], d_flags);
+      }
       validate_vectors_kernel<<<nblk(std::max<int64_t>(m, p.n)), 256, 0, stream_>>>(p.c, p.rhs, p.lb, p.ub,
                                                                                      m, p.n, d_flags);
       int flags = 0;

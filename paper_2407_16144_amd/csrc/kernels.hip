@@ -1414,38 +1414,6 @@ __global__ void copy_state_kernel(const T* src, double* dst, int64_t off, int64_
   if (i < n) dst[i] = (double)src[off + i];
 }
 
-// flags: 1 bad row pointers, 2 column out of range or not increasing, 4 non-finite value
-__global__ void validate_csr_kernel(const int32_t* rp, const int32_t* ci, const double* val, int64_t m,
-                                    int64_t n, int64_t nnz, int* flags) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r == 0 && (rp[0] != 0 || rp[m] != nnz)) atomicOr(flags, 1);
-  if (r >= m) return;
-  const int64_t p0 = rp[r], p1 = rp[r + 1];
-  if (p1 < p0 || p0 < 0 || p1 > nnz) {
-    atomicOr(flags, 1);
-    return;
-  }
-  int64_t prev = -1;
-  for (int64_t e = p0; e < p1; ++e) {
-    const int64_t c = ci[e];
-    if (c < 0 || c >= n || c <= prev) atomicOr(flags, 2);
-    prev = c;
-    if (!isfinite(val[e])) atomicOr(flags, 4);
-  }
-}
-
-// flags: 8 non-finite c or rhs, 16 bad bounds
-__global__ void validate_vectors_kernel(const double* c, const double* rhs, const double* lb,
-                                        const double* ub, int64_t m, int64_t n, int* flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m && !isfinite(rhs[i])) atomicOr(flags, 8);
-  if (i < n) {
-    if (!isfinite(c[i])) atomicOr(flags, 8);
-    const double a = lb[i], b = ub[i];
-    if (isnan(a) || isnan(b) || a > b || a == INFINITY || b == -INFINITY) atomicOr(flags, 16);
-  }
-}
-
 __global__ void set_limit_status_kernel(InstState* st, int* status_out, int ninst, int code) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ninst && st[i].status == ST_RUNNING) {

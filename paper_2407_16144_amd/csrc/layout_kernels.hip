@@ -1,10 +1,51 @@
-// Kernels that build the matrix layouts at lp_create (and when a batch
-// re-blocks its last LPs): the explicit transpose K^T, column slicing, the
-// sort keys of column-sorted blocks and groups and the gathers that apply a
-// sorted permutation.  None of them runs in a solver step.  Included by
-// engine.hip after kernels.hip (shared types from halp_types.h).
+// Kernels of lp_create (and of an engine that re-blocks its last LPs) that
+// never run in a solver step: validation of device-resident input, the
+// explicit transpose K^T, column slicing, the sort keys of column-sorted
+// blocks and groups and the gathers that apply a sorted permutation.
+// Included by engine.hip after kernels.hip (shared types from halp_types.h).
 
 namespace halp {
+
+// flags: 1 bad row pointers, 2 column out of range or not increasing, 4 non-finite value
+__global__ void validate_rowptr_kernel(const int32_t* rp, int64_t m, int64_t nnz, int* flags) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0 && (rp[0] != 0 || rp[m] != nnz)) atomicOr(flags, 1);
+  if (r >= m) return;
+  if (rp[r + 1] < rp[r] || rp[r] < 0 || rp[r + 1] > nnz) atomicOr(flags, 1);
+}
+
+// One thread per entry: column in range and strictly above the previous
+// entry's unless the entry starts its row (found by a binary search of the
+// row pointers: the last row whose start is at or before it), finite value.
+// The search stays within rp[0..m] whatever the row pointers hold; invalid
+// row pointers are flagged by validate_rowptr_kernel.
+__global__ void validate_entries_kernel(const int32_t* rp, const int32_t* ci, const double* val, int64_t m,
+                                        int64_t n, int64_t nnz, int* flags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int64_t c = ci[e];
+  if (c < 0 || c >= n) atomicOr(flags, 2);
+  if (!isfinite(val[e])) atomicOr(flags, 4);
+  if (e == 0) return;
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if ((int64_t)rp[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  if ((int64_t)rp[lo] != e && c <= (int64_t)ci[e - 1]) atomicOr(flags, 2);
+}
+
+// flags: 8 non-finite c or rhs, 16 bad bounds
+__global__ void validate_vectors_kernel(const double* c, const double* rhs, const double* lb,
+                                        const double* ub, int64_t m, int64_t n, int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && !isfinite(rhs[i])) atomicOr(flags, 8);
+  if (i < n) {
+    if (!isfinite(c[i])) atomicOr(flags, 8);
+    const double a = lb[i], b = ub[i];
+    if (isnan(a) || isnan(b) || a > b || a == INFINITY || b == -INFINITY) atomicOr(flags, 16);
+  }
+}
 
 __global__ void shift_copy_kernel(int32_t* dst, const int32_t* src, int64_t n, int64_t add) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -259,6 +259,47 @@ def test_device_inputs_equal_host_inputs():
     assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
 
 
+def _device_create(lp, rowptr=None, col=None, val=None):
+    t = lambda a, dt: torch.as_tensor(np.asarray(a), dtype=dt, device="cuda").contiguous()
+    args = (t(lp.rowptr if rowptr is None else rowptr, torch.int32), t(lp.col if col is None else col, torch.int32),
+            t(lp.val if val is None else val, torch.float64), t(lp.c, torch.float64), t(lp.rhs, torch.float64),
+            t(lp.lb, torch.float64), t(lp.ub, torch.float64))
+    h = halp.lp_create(lp.n, lp.m_eq, lp.m_ineq, *args, inputs_on_device=1)
+    halp.lp_destroy(h)
+
+
+def test_device_inputs_validated_on_the_device():
+    """Device-resident CSR input is validated by kernels (row pointers per
+    row, entries one per thread): a column out of range, columns not
+    strictly increasing within a row, a NaN value or decreasing row
+    pointers are rejected with LP_ERR_INVALID; empty rows (first, inner,
+    last) are accepted."""
+    lp = lpgen.scaled_powerlaw(31, 300, 1200)
+    print("case device validation", flush=True)
+    _device_create(lp)
+    rp, col, val = lp.rowptr.copy(), lp.col.copy(), lp.val.copy()
+    long_row = int(np.argmax(np.diff(rp)))
+    a, b = int(rp[long_row]), int(rp[long_row + 1])
+    cases = []
+    c = col.copy(); c[b - 1] = lp.n; cases.append(("column = n", None, c, None))
+    c = col.copy(); c[a] = -1; cases.append(("negative column", None, c, None))
+    c = col.copy(); c[a + 1], c[a + 2] = c[a + 2], c[a + 1]; cases.append(("unsorted row", None, c, None))
+    c = col.copy(); c[a + 1] = c[a]; cases.append(("duplicate column", None, c, None))
+    v = val.copy(); v[len(v) // 2] = np.nan; cases.append(("NaN value", None, None, v))
+    r = rp.copy(); r[5] = r[6] + 1; cases.append(("decreasing row_ptr", r, None, None))
+    for name, r_, c_, v_ in cases:
+        with pytest.raises(halp.HalpError) as ei:
+            _device_create(lp, r_, c_, v_)
+        assert ei.value.code == halp.LP_ERR_INVALID, name
+    # empty rows (the first, one inside, the last): their entries removed --
+    # accepted
+    for k in (0, 7, lp.m - 1):
+        a, b = int(rp[k]), int(rp[k + 1])
+        r = rp.copy()
+        r[k + 1:] -= b - a
+        _device_create(lp, r, np.delete(col, np.arange(a, b)), np.delete(val, np.arange(a, b)))
+
+
 @pytest.mark.parametrize("det", [True, False])
 def test_batch_results_equal_single_results(det):
     """Each LP of a ragged batch gives bit-identical results to solving it
