@@ -140,13 +140,19 @@ __global__ __launch_bounds__(kThreads) void block_keys_kernel(const Blk* blks, c
   const Blk b = blks[blockIdx.x];
   const uint64_t hi = (uint64_t)blockIdx.x << 32;
   if (blk_kind(b) == BK_SORTED) {
+    // one thread per entry; its row is the last of the block's rows that
+    // starts at or before it (empty rows share the next row's start)
     const int rb = blk_rowbits(b);
     const int nrows = b.r1 - b.r0;
-    for (int r = threadIdx.x; r < nrows; r += kThreads) {
-      for (int32_t e = rp[b.r0 + r]; e < rp[b.r0 + r + 1]; ++e) {
-        key[e - nz0] = hi | (((uint32_t)(ci[e] - b.rp_off) << rb) | (uint32_t)r);
-        src[e - nz0] = e;
+    for (int k = threadIdx.x; k < b.pn; k += kThreads) {
+      const int32_t e = b.p0 + k;
+      int lo = 0, up = nrows - 1;
+      while (lo < up) {
+        const int mid = (lo + up + 1) >> 1;
+        if (rp[b.r0 + mid] <= e) lo = mid; else up = mid - 1;
       }
+      key[e - nz0] = hi | (((uint32_t)(ci[e] - b.rp_off) << rb) | (uint32_t)lo);
+      src[e - nz0] = e;
     }
   } else {
     for (int e = threadIdx.x; e < b.pn; e += kThreads) {
