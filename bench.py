@@ -254,7 +254,7 @@ def serial_solve(halp, lps, tol, max_iter, method):
     return solved, time.perf_counter() - t0
 
 
-def run_batch(args):
+def run_batch(args, copy=None):
     """512 power-law LPs of uneven size (10% primal infeasible) solved as one
     batch: per step, create (device-resident inputs) + solve of all of them."""
     import torch
@@ -315,7 +315,11 @@ def run_batch(args):
     finally:
         halp.lp_batch_destroy(hp)
     roofline = batch_roofline(bulk, s, not args.fixed_order)
+    if not args.fixed_order:
+        roofline["traffic"] = measured_traffic(f"batch-{args.precision}", roofline["kernel"])
     roofline["sampled"] = "first 1,280 iterations of the whole batch, every chunk timed"
+    if copy is not None:
+        roofline["copy_kernel"] = copy
     roofline["timed_run"] = batch_roofline(ksum, s, not args.fixed_order)
     st = [r["status"] for r in res]
     out = {"metric": "solved LPs/s + p99 latency at 1e-4 rel. KKT; SpMV HBM GB/s vs peak",
@@ -465,11 +469,13 @@ def main():
     import paper_2407_16144_amd as halp
 
     torch.cuda.set_device(0)
-    if args.workload in ("batch", "serve"):
-        out = run_batch(args) if args.workload == "batch" else run_serve(args)
-        print(json.dumps(out), flush=True)
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
         return
     copy = copy_probe(torch, args.copy_probe_mb if args.copy_probe_mb > 0 else 1024.0)
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args, copy)), flush=True)
+        return
     print(f"copy probe: {copy['bytes_per_launch']} B per launch at {copy['GBs']:.0f} GB/s", file=sys.stderr,
           flush=True)
     if args.workload == "mps":
