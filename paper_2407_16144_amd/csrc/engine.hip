@@ -467,6 +467,8 @@ class Engine final : public EngineBase {
   T *kt1_ = nullptr, *kt2_ = nullptr, *kx1_ = nullptr, *kx2_ = nullptr;  // sorted blocks' eval products
   uint8_t *actx = nullptr, *acty = nullptr;  // activity at the last check (two-stage diagnostics)
   Blk *d_schedPS = nullptr, *d_schedDS = nullptr;
+  int* d_live_ = nullptr;       // slot ids of the LPs in the current schedules (control kernel)
+  int64_t cap_live_ = 0;
   int64_t capPS_ = 0, capDS_ = 0, nPS_ = 0, nDS_ = 0;
   // control
   InstState* d_st = nullptr;
@@ -596,6 +598,7 @@ void Engine<T>::release_all() {
   dfree(spartP);
   dfree(d_schedPS);
   dfree(d_schedDS);
+  dfree(d_live_);
   dfree(d_st);
   dfree(d_status);
   dfree(d_cnt);
@@ -1814,6 +1817,13 @@ void Engine<T>::rebuild_schedules() {
     if (n) HIPCHECK(hipMemcpyAsync(d, v.data(), sizeof(Blk) * n, hipMemcpyHostToDevice, stream_));
   };
   scheduled_ = (int)live.size();
+  if ((int64_t)live.size() > cap_live_) {
+    dfree(d_live_);
+    cap_live_ = std::max<int64_t>((int64_t)live.size(), 2 * cap_live_);
+    dalloc(&d_live_, cap_live_);
+  }
+  if (!live.empty())
+    HIPCHECK(hipMemcpyAsync(d_live_, live.data(), sizeof(int) * live.size(), hipMemcpyHostToDevice, stream_));
   upload(P, d_schedP, capP_, nP_, &partP);
   upload(D, d_schedD, capD_, nD_, &partD);
   upload(PS, d_schedPS, capPS_, nPS_, nullptr);
@@ -1922,7 +1932,8 @@ void Engine<T>::launch_chunk() {
         HIPCHECK(hipEventRecord(e[4], stream_));
         HIPCHECK(hipEventRecord(e[5], stream_));  // empty pair: the events' own cost
       }
-      control_kernel<<<(unsigned)nslots_, kThreads, 0, stream_>>>(d_st, partP, partD, d_gbase, i, d_status);
+      control_kernel<<<(unsigned)scheduled_, kThreads, 0, stream_>>>(d_st, d_live_, partP, partD, d_gbase, i,
+                                                                     d_status);
     }
   };
   if (prof) {

@@ -1044,12 +1044,12 @@ __global__ __launch_bounds__(kThreads) void dual_step(IterArgs<T> A, int step) {
 // partial sums, then the controller.  A kernel of its own, so that the
 // partial sums of every XCD are visible without device-scope fences inside
 // the step kernels (each of which would write back the XCD's L2).
-__global__ __launch_bounds__(kThreads) void control_kernel(InstState* st, const double* partP,
+__global__ __launch_bounds__(kThreads) void control_kernel(InstState* st, const int* ids, const double* partP,
                                                            const double* partD, const int64_t* gbase,
                                                            int step, int* status_out) {
   __shared__ double s_red[kThreads / 64][kNS];
   __shared__ double s_sum[2][kNS];
-  const int inst = blockIdx.x;
+  const int inst = ids[blockIdx.x];  // the LPs in the current schedules
   InstState& S = st[inst];
   const int64_t g = *gbase + step;
   const int mode = step_mode(S, g);
