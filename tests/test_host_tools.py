@@ -72,3 +72,24 @@ def test_kernel_bytes_split():
     assert bench.kernel_bytes(n, m, nnz, s, False, False, True) == plain
     ps = bench.kernel_bytes(n, m, nnz, s, False, False, False, True)
     assert ps["primal_step"] == p - 4 * (n + 1) and ps["dual_step"] == d - 4 * (m + 1)
+
+
+def test_measured_traffic_lookup(tmp_path, monkeypatch):
+    """The benchmark reads a kernel's HBM bytes from the committed counter
+    summary only while the kernel sources are unchanged, and names a kernel
+    by the prefix of its templated name."""
+    import json
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    good = {"source_sha256": rs.kernel_source_hash(),
+            "kernels": {"sorted_group_step<double, true, 512, true>": {"traffic_bytes": 381.4e6},
+                        "sorted_group_step<double, false, 512, true>": {"traffic_bytes": 378.6e6},
+                        "dual_step<double>": {"traffic_bytes": 50.4e6}}}
+    (prof / "traffic_w.json").write_text(json.dumps(good))
+    (prof / "traffic_old.json").write_text(json.dumps({**good, "source_sha256": "0" * 64}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("w", "sorted_group_step<double, true") == 381400000
+    assert bench.measured_traffic("w", "dual_step") == 50400000
+    assert bench.measured_traffic("w", "sorted_group_step<double") is None     # two kernels match
+    assert bench.measured_traffic("old", "dual_step") is None                  # sources changed since
+    assert bench.measured_traffic("none", "dual_step") is None                 # no summary
