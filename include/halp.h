@@ -140,23 +140,31 @@ typedef struct {
                                off into their own strided tiles) */
   int slice_entries;        /* entries per column-slice tile: 256, 512 (default) or 1024 */
   int slice_rows;           /* rows per sliced row group, 1..256 (default 128) */
-  int slice_sort;           /* sliced K (dual product): 1 (default) stores each slice tile's
-                               entries in column order, sort_rows rows per tile, and adds
-                               the products into the row sums with LDS atomics (faster;
-                               the order of the additions within a row, and so the last
-                               bits of the iterates, may differ from run to run); 0: rows in
-                               order with fixed-order sums (slice_entries, slice_rows) */
-  int sort_rows;            /* most rows per sorted group, 1..16384 (default 16384): the
-                               engine takes the largest group that leaves at least 480
-                               workgroups per product and fits the packed column index
-                               (fewer rows when a slice is wider than
-                               2^(32 - log2 rows)); column-sorted plain blocks take at
-                               most 2048 of them, and at most max(256, rows / 64) */
-  int plain_sort;           /* products that are not column-sliced (K^T of the large LP,
-                               both products of small LPs): 1 (default) stores the rows of
-                               at most 1024 entries in column-sorted blocks of sort_rows
-                               (<= 2048) rows with LDS-atomic row sums (same caveat as
-                               slice_sort); 0: plain tiles (tile_rows) with fixed-order sums */
+  int slice_sort;           /* 1 (default): products whose gathered vector exceeds
+                               slice_min_bytes, and products large enough for sorted
+                               groups of more rows than a plain block, are stored in
+                               sorted groups (row groups x column slices, entries in
+                               column order) whose products are added into the row sums
+                               with LDS atomics (faster; the order of the additions
+                               within a row, and so the last bits of the iterates, may
+                               differ from run to run); 0: sliced products in row-major
+                               slice tiles with fixed-order sums (slice_entries,
+                               slice_rows) */
+  int sort_rows;            /* most rows per sorted group or column-sorted block,
+                               1..16384 (default 16384).  Sorted groups: the largest
+                               group that leaves at least group_blocks workgroups per
+                               product and fits the packed column index (fewer rows when
+                               a slice is wider than 2^(32 - log2 rows)).  Column-sorted
+                               plain blocks: at most 2048 rows, sized for the LPs that
+                               share the launches: max(256, rows / 64) with 12 or more
+                               live LPs, else about 768 workgroups per product over the
+                               live LPs (down to 64 rows); engines re-block their
+                               running LPs as others finish */
+  int plain_sort;           /* products neither sliced nor in sorted groups (those of
+                               small and mid-size LPs): 1 (default) stores the rows of at
+                               most 1024 entries in column-sorted blocks (see sort_rows)
+                               with LDS-atomic row sums (same caveat as slice_sort);
+                               0: plain tiles (tile_rows) with fixed-order sums */
   int group_threads;        /* threads per workgroup of the sorted-group slice kernels:
                                256, 512 or 1024; 0 (default): enough for about eight
                                waves per CU over the product's workgroups */

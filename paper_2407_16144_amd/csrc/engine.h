@@ -62,8 +62,8 @@ struct Options {
   int tile_rows = kMaxRows;        // rows per plain workgroup tile (<= 256)
   int slice_entries = kSliceNB;    // entries per slice tile: 256, 512 or 1024
   int slice_rows = kSliceRows;     // rows per sliced row group (<= 256)
-  int slice_sort = 1;              // sliced K: column-sorted tiles, LDS-atomic row sums
-  int plain_sort = 1;              // unsliced K / K^T: column-sorted blocks, LDS-atomic row sums
+  int slice_sort = 1;              // sliced / large products: sorted groups, LDS-atomic row sums
+  int plain_sort = 1;              // other products: column-sorted blocks, LDS-atomic row sums
   int sort_rows = kSortRows;       // most rows per sorted group (plain sorted blocks: at most kSortRowsPlain)
   int group_threads = 0;           // threads per workgroup of the sorted-group slice kernels: 256, 512, 1024; 0: by size
   int group_batched = 1;           // 1: a thread's gathers issued together; 0: one gather per LDS add
