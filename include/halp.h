@@ -222,6 +222,16 @@ int lp_create(lp_solver** out, int64_t n, int64_t m_eq, int64_t m_ineq, const in
               const double* lb, const double* ub, int inputs_on_device, void* stream,
               const lp_options* opt);
 
+/* lp_create for CSR input whose row pointers are 64-bit (int64_t, m + 1
+ * entries, host or device memory like the other arrays); every entry must
+ * lie in [0, 2^31 - 1] (the solver stores at most 2^31 - 1 entries per LP),
+ * else LP_ERR_INVALID.  Device row pointers are narrowed on `stream` into a
+ * temporary int32 array that the call frees before it returns. */
+int lp_create64(lp_solver** out, int64_t n, int64_t m_eq, int64_t m_ineq, const int64_t* row_ptr,
+                const int32_t* col_idx, const double* val, const double* c, const double* rhs,
+                const double* lb, const double* ub, int inputs_on_device, void* stream,
+                const lp_options* opt);
+
 /* Runs restarted (reflected) Halpern PDHG until the relative KKT error at the
  * check candidate T(z) is <= rel_kkt_tol (LP_OPTIMAL), an infeasibility
  * certificate passes its Farkas test, the first check at or after max_iter

@@ -86,6 +86,8 @@ _sig = {
     "lp_last_error": (C.c_char_p, []),
     "lp_create": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, _P,
                             C.c_int, _P, _P]),
+    "lp_create64": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P, _P,
+                              C.c_int, _P, _P]),
     "lp_solve": (C.c_int, [_P, C.c_double, C.c_int64, C.c_double]),
     "lp_status": (C.c_int, [_P, _P]),
     "lp_get_solution": (C.c_int, [_P, _P, _P, C.c_int]),
@@ -157,17 +159,18 @@ def lp_default_options(**overrides) -> lp_options:
     return o
 
 
-def _marshal_problem(n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub, on_device):
+def _marshal_problem(n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub, on_device, rp_type=np.int32):
     keep = []
     ptrs = []
-    for a, dt in ((row_ptr, np.int32), (col_idx, np.int32), (val, np.float64), (c, np.float64),
+    tdt = {np.int32: "torch.int32", np.int64: "torch.int64", np.float64: "torch.float64"}
+    for a, dt in ((row_ptr, rp_type), (col_idx, np.int32), (val, np.float64), (c, np.float64),
                   (rhs, np.float64), (lb, np.float64), (ub, np.float64)):
         if on_device:
             if a is None:
                 ptrs.append(None)
                 continue
-            if a.dtype != {np.int32: torch.int32, np.float64: torch.float64}[dt] or not a.is_contiguous():
-                raise TypeError("device inputs must be contiguous int32 / float64 tensors")
+            if str(a.dtype) != tdt[dt] or not a.is_contiguous():
+                raise TypeError("device inputs must be contiguous tensors of the documented types")
             ptrs.append(a.data_ptr())
         else:
             if a is None:
@@ -189,6 +192,18 @@ def lp_create(n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub, inputs_on_
     h = C.c_void_p()
     _check(_lib.lp_create(C.byref(h), n, m_eq, m_ineq, *ptrs, int(inputs_on_device),
                           stream, C.byref(opt) if opt is not None else None))
+    del keep
+    return h
+
+
+def lp_create64(n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub, inputs_on_device=0,
+                stream=None, opt=None):
+    """lp_create with int64 row pointers; returns an opaque handle."""
+    ptrs, keep = _marshal_problem(n, m_eq, m_ineq, row_ptr, col_idx, val, c, rhs, lb, ub,
+                                  inputs_on_device, rp_type=np.int64)
+    h = C.c_void_p()
+    _check(_lib.lp_create64(C.byref(h), n, m_eq, m_ineq, *ptrs, int(inputs_on_device),
+                            stream, C.byref(opt) if opt is not None else None))
     del keep
     return h
 

@@ -462,6 +462,44 @@ int lp_create(lp_solver** out, int64_t n, int64_t m_eq, int64_t m_ineq, const in
   });
 }
 
+int lp_create64(lp_solver** out, int64_t n, int64_t m_eq, int64_t m_ineq, const int64_t* row_ptr,
+                const int32_t* col_idx, const double* val, const double* c, const double* rhs, const double* lb,
+                const double* ub, int inputs_on_device, void* stream, const lp_options* opt) {
+  return guarded([&]() -> int {
+    if (!out) return fail(LP_ERR_INVALID, "null output handle");
+    *out = nullptr;
+    if (!row_ptr) return fail(LP_ERR_INVALID, "null row_ptr");
+    if (m_eq < 0 || m_ineq < 0) return fail(LP_ERR_INVALID, "sizes must satisfy n >= 1, m >= 0");
+    const int64_t m = m_eq + m_ineq;
+    if (!inputs_on_device) {
+      std::vector<int32_t> rp(m + 1);
+      for (int64_t i = 0; i <= m; ++i) {
+        if (row_ptr[i] < 0 || row_ptr[i] > (int64_t)INT32_MAX)
+          return fail(LP_ERR_INVALID, "row_ptr entry outside [0, 2^31 - 1] (at most 2^31 - 1 stored entries)");
+        rp[i] = (int32_t)row_ptr[i];
+      }
+      return lp_create(out, n, m_eq, m_ineq, rp.data(), col_idx, val, c, rhs, lb, ub, 0, stream, opt);
+    }
+    int32_t* rp = nullptr;
+    if (hipMalloc((void**)&rp, sizeof(int32_t) * (m + 1)) != hipSuccess)
+      return fail(LP_ERR_OOM, "device allocation failed");
+    int rc = LP_OK;
+    try {
+      if (halp::narrow_row_ptr(row_ptr, rp, m + 1, (hipStream_t)stream))
+        rc = fail(LP_ERR_INVALID, "row_ptr entry outside [0, 2^31 - 1] (at most 2^31 - 1 stored entries)");
+      else
+        rc = lp_create(out, n, m_eq, m_ineq, rp, col_idx, val, c, rhs, lb, ub, 1, stream, opt);
+      // lp_create copies its inputs on the handle's stream: wait for it
+      if (rc == LP_OK) hip_ok(hipStreamSynchronize((*out)->stream.s), "stream synchronize");
+    } catch (...) {
+      (void)hipFree(rp);
+      throw;
+    }
+    (void)hipFree(rp);
+    return rc;
+  });
+}
+
 int lp_solve(lp_solver* s, double tol, int64_t max_iter, double time_limit_s) {
   return guarded([&]() -> int {
     if (!s) return fail(LP_ERR_INVALID, "null handle");

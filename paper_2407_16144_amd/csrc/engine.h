@@ -161,6 +161,9 @@ class WorkspaceScope {
 
 // Host-side validation of a host-memory LP (throws Error(-1, ...)); needs no GPU.
 void validate_host_problem(const Problem& p);
+// Device int64 row pointers narrowed into int32 (dst, count entries) on
+// `stream`; returns nonzero when an entry is negative or above 2^31 - 1.
+int narrow_row_ptr(const int64_t* src, int32_t* dst, int64_t count, hipStream_t stream);
 
 // capacity: sizes of the three spaces and the slot count (0 = grow to fit)
 std::unique_ptr<EngineBase> make_engine(const Options& opt, hipStream_t stream, int64_t cap_m,

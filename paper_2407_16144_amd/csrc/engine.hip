@@ -2227,6 +2227,20 @@ void Engine<T>::stored_matrix(int id, bool transpose, int32_t* rp, int32_t* ci, 
   for (int64_t e = 0; e < S.nnz; ++e) ci[e] -= (int32_t)c0;
 }
 
+int narrow_row_ptr(const int64_t* src, int32_t* dst, int64_t count, hipStream_t stream) {
+  if (count <= 0) return 0;
+  int* d_bad = nullptr;
+  dalloc(&d_bad, 1);
+  HIPCHECK(hipMemsetAsync(d_bad, 0, sizeof(int), stream));
+  narrow_row_ptr_kernel<<<nblk(count), 256, 0, stream>>>(src, dst, count, d_bad);
+  HIPCHECK(hipGetLastError());
+  int bad = 0;
+  HIPCHECK(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
+  dfree(d_bad);
+  return bad;
+}
+
 std::unique_ptr<EngineBase> make_engine(const Options& opt, hipStream_t stream, int64_t cap_m, int64_t cap_n,
                                         int64_t cap_nnz, int max_slots) {
   if (opt.precision == 1)

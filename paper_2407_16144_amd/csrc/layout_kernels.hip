@@ -6,6 +6,20 @@
 
 namespace halp {
 
+// dst = src narrowed to int32 (row pointers given as int64); *bad = 1 when an
+// entry is negative or above 2^31 - 1 (that entry is written as 0)
+__global__ void narrow_row_ptr_kernel(const int64_t* src, int32_t* dst, int64_t n, int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t v = src[i];
+  if (v < 0 || v > (int64_t)INT32_MAX) {
+    atomicOr(bad, 1);
+    dst[i] = 0;
+  } else {
+    dst[i] = (int32_t)v;
+  }
+}
+
 // flags: 1 bad row pointers, 2 column out of range or not increasing, 4 non-finite value
 __global__ void validate_rowptr_kernel(const int32_t* rp, int64_t m, int64_t nnz, int* flags) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -103,6 +103,28 @@ static void malformed_lps(void) {
   }
 }
 
+static void row_ptr64(void) {
+  Tiny t;
+  tiny(&t);
+  int64_t rp[4] = {0, 2, 5, 7};
+  lp_solver* h = (lp_solver*)0x1;
+  EXPECT(lp_create64(NULL, t.n, t.m_eq, t.m_ineq, rp, t.ci, t.val, t.c, t.rhs, t.lb, t.ub, 0, NULL, NULL) ==
+             LP_ERR_INVALID, "lp_create64(NULL out)");
+  EXPECT(lp_create64(&h, t.n, t.m_eq, t.m_ineq, NULL, t.ci, t.val, t.c, t.rhs, t.lb, t.ub, 0, NULL, NULL) ==
+             LP_ERR_INVALID, "lp_create64(NULL row_ptr)");
+  rp[2] = (int64_t)1 << 33;
+  EXPECT(lp_create64(&h, t.n, t.m_eq, t.m_ineq, rp, t.ci, t.val, t.c, t.rhs, t.lb, t.ub, 0, NULL, NULL) ==
+             LP_ERR_INVALID, "lp_create64(row_ptr above 2^31 - 1)");
+  rp[2] = -5;
+  EXPECT(lp_create64(&h, t.n, t.m_eq, t.m_ineq, rp, t.ci, t.val, t.c, t.rhs, t.lb, t.ub, 0, NULL, NULL) ==
+             LP_ERR_INVALID, "lp_create64(negative row_ptr)");
+  rp[2] = 5;
+  t.ci[1] = 9;
+  EXPECT(lp_create64(&h, t.n, t.m_eq, t.m_ineq, rp, t.ci, t.val, t.c, t.rhs, t.lb, t.ub, 0, NULL, NULL) ==
+             LP_ERR_INVALID, "lp_create64(column out of range)");
+  EXPECT(h == NULL, "lp_create64: handle set on failure");
+}
+
 static void invalid_options(void) {
   Tiny t;
   tiny(&t);
@@ -280,6 +302,7 @@ int main(void) {
   lp_default_options(&o);
   EXPECT(o.method == 1 && o.precision == 0, "defaults");
   malformed_lps();
+  row_ptr64();
   invalid_options();
   null_handles();
   random_malformed(2000);

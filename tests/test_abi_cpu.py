@@ -123,3 +123,15 @@ def test_package_fails_loudly_without_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", "import paper_2407_16144_amd"], cwd=tmp_path,
                        capture_output=True, text=True)
     assert r.returncode != 0 and "libhalp.so not built" in r.stderr
+
+
+def test_int64_row_pointers_checked_on_host():
+    a = _tiny_arrays()
+    rp = np.asarray(a["row_ptr"], dtype=np.int64)
+    for bad, what in ((2**31, "above 2^31 - 1"), (-1, "negative")):
+        r = rp.copy()
+        r[1] = bad
+        with pytest.raises(halp.HalpError) as ei:
+            halp.lp_create64(a["n"], a["m_eq"], a["m_ineq"], r, a["col_idx"], a["val"], a["c"], a["rhs"],
+                             a["lb"], a["ub"])
+        assert ei.value.code == halp.LP_ERR_INVALID, what

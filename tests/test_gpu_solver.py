@@ -259,6 +259,39 @@ def test_device_inputs_equal_host_inputs():
     assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
 
 
+def test_int64_row_pointers_equal_int32():
+    """lp_create64 (int64 row pointers, host or device) gives the same solve,
+    bit for bit in fixed-order mode, as lp_create."""
+    lp = lpgen.scaled_powerlaw(33, 400, 1400)
+    print("case row_ptr int64", flush=True)
+    opt = halp.lp_default_options(**DET)
+    ref, xr, yr, _ = halp.solve_lp(lp, tol=1e-6, max_iter=200_000, opt=opt)
+    t = lambda a, dt: torch.as_tensor(np.asarray(a), dtype=dt, device="cuda").contiguous()
+    for on_device in (0, 1):
+        if on_device:
+            args = (t(lp.rowptr.astype(np.int64), torch.int64), t(lp.col, torch.int32), t(lp.val, torch.float64),
+                    t(lp.c, torch.float64), t(lp.rhs, torch.float64), t(lp.lb, torch.float64),
+                    t(lp.ub, torch.float64))
+        else:
+            args = (lp.rowptr.astype(np.int64), lp.col, lp.val, lp.c, lp.rhs, lp.lb, lp.ub)
+        h = halp.lp_create64(lp.n, lp.m_eq, lp.m_ineq, *args, inputs_on_device=on_device, opt=opt)
+        try:
+            halp.lp_solve(h, 1e-6, 200_000)
+            r = halp.lp_status(h).as_dict()
+            x, y = halp.lp_get_solution(h, lp.n, lp.m)
+        finally:
+            halp.lp_destroy(h)
+        assert r["status"] == ref["status"] and r["iters"] == ref["iters"], (on_device, r)
+        assert np.array_equal(x, xr) and np.array_equal(y, yr), on_device
+    bad = lp.rowptr.astype(np.int64)
+    bad[3] = 2**31
+    with pytest.raises(halp.HalpError) as ei:
+        halp.lp_create64(lp.n, lp.m_eq, lp.m_ineq, t(bad, torch.int64), t(lp.col, torch.int32),
+                         t(lp.val, torch.float64), t(lp.c, torch.float64), t(lp.rhs, torch.float64),
+                         t(lp.lb, torch.float64), t(lp.ub, torch.float64), inputs_on_device=1)
+    assert ei.value.code == halp.LP_ERR_INVALID
+
+
 def _device_create(lp, rowptr=None, col=None, val=None):
     t = lambda a, dt: torch.as_tensor(np.asarray(a), dtype=dt, device="cuda").contiguous()
     args = (t(lp.rowptr if rowptr is None else rowptr, torch.int32), t(lp.col if col is None else col, torch.int32),
